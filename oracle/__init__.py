@@ -1,0 +1,300 @@
+"""FP64 CPU oracle for the relativistic lattice Boltzmann step (TEST INFRASTRUCTURE).
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+(``paper_0912_2913_amd``) and never imports it; the two meet only through the
+seeded input generators in ``rlb_inputs``.
+
+Contents:
+  * ``liboracle_rlb.so`` (built from ``rlb_oracle.cpp``): the D3Q19 two-population
+    scheme of the paper (eqs. lbe1/lbe2, equil1s/equil2as/equil2bs, the macroscopic
+    constraints closed by e = 3P), plain single-threaded loops, templated on the
+    scalar so that complex-step derivatives are exact references.
+  * ``d1q3``: an independent lumped one-dimensional form of the same scheme.
+  * ``riemann``: the exact ideal Riemann solution for P = e/3 (convergence target).
+
+Layout of every array passed here: populations ``[2][19][cells]`` (f then g; the
+g-only calls take ``[19][cells]``), fields ``[cells]``, velocities ``[3][cells]``;
+``cells = batch*nz*ny*nx`` with x fastest.  Boundary codes: 0 periodic, 1 outflow
+(zero-gradient copy), 2 inflow (face held at the inflow equilibrium).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle_rlb.so")
+_lib = None
+
+PERIODIC, OUTFLOW, INFLOW = 0, 1, 2
+Q = 19
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_lp = ctypes.POINTER(ctypes.c_long)
+
+
+def lib():
+    """Load (building first if absent or stale) the oracle library."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    src = os.path.join(_HERE, "rlb_oracle.cpp")
+    if (not os.path.exists(_LIB_PATH)) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        _build.build()
+    L = ctypes.CDLL(_LIB_PATH)
+    L.ora_lattice.argtypes = [_ip, _dp, _ip]
+    L.ora_equilibria.argtypes = [ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double, _dp, _dp]
+    L.ora_invert.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp]
+    L.ora_invert.restype = ctypes.c_int
+    L.ora_collide.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, _dp, _dp]
+    L.ora_collide.restype = ctypes.c_int
+    common = [_ip, ctypes.c_double, _ip, _dp, _u8p]
+    L.ora_init.argtypes = common + [_dp, _dp, _dp, _dp]
+    L.ora_run.argtypes = common + [_dp, _dp, ctypes.c_int]
+    L.ora_run.restype = ctypes.c_long
+    L.ora_run_g.argtypes = common + [_dp, _dp, ctypes.c_int]
+    L.ora_run_g.restype = ctypes.c_long
+    L.ora_update_cells.argtypes = common + [_dp, _dp, ctypes.c_long, _lp, _dp]
+    L.ora_moments.argtypes = [_ip, ctypes.c_double, _u8p, _dp, _dp, _dp, _dp, _dp]
+    L.ora_adjoint_step.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.ora_moments_adjoint.argtypes = [_ip, ctypes.c_double, _u8p, _dp, _dp, _dp, _dp]
+    L.ora_init_adjoint.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.ora_loss.argtypes = common + [_dp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp]
+    L.ora_loss.restype = ctypes.c_double
+    L.ora_loss_cs.argtypes = common + [_dp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp,
+                                       _dp, _dp, _dp, _dp, _dp]
+    L.ora_loss_cs.restype = ctypes.c_double
+    L.ora_gradient.argtypes = common + [_dp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp,
+                                        _dp, _dp, _dp, _dp]
+    L.ora_gradient.restype = ctypes.c_double
+    _lib = L
+    return L
+
+
+def _d(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> Optional[np.ndarray]:
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+@dataclass
+class Problem:
+    """A lattice problem in the oracle's terms (all host data, FP64)."""
+
+    nx: int
+    ny: int
+    nz: int
+    batch: int = 1
+    c_l: float = 1.0
+    bc: Sequence[Sequence[int]] = ((0, 0), (0, 0), (0, 0))
+    inflow: Sequence[float] = (1.0, 1.0, 0.0, 0.0, 0.0)  # n, e, beta_x, beta_y, beta_z
+    tau: Sequence[float] = (0.6,)
+    solid: Optional[np.ndarray] = None  # uint8 [cells]
+
+    @property
+    def cells(self) -> int:
+        return self.batch * self.nz * self.ny * self.nx
+
+    def _args(self):
+        dims = np.array([self.nx, self.ny, self.nz, self.batch], dtype=np.int32)
+        bc = np.array([v for ax in self.bc for v in ax], dtype=np.int32)
+        inflow = np.array(self.inflow, dtype=np.float64)
+        solid = None
+        if self.solid is not None:
+            solid = np.ascontiguousarray(self.solid.reshape(-1).astype(np.uint8))
+            assert solid.size == self.cells
+        tau = np.array(self.tau, dtype=np.float64).reshape(-1)
+        if tau.size == 1 and self.batch > 1:
+            tau = np.full(self.batch, tau[0])
+        assert tau.size == self.batch
+        self._keep = (dims, bc, inflow, solid, tau)
+        return (dims.ctypes.data_as(_ip), ctypes.c_double(self.c_l), bc.ctypes.data_as(_ip),
+                inflow.ctypes.data_as(_dp),
+                solid.ctypes.data_as(_u8p) if solid is not None else None), tau
+
+
+def lattice():
+    """(e[19][3], w[19], opp[19]) as the oracle defines them."""
+    e = np.zeros((Q, 3), np.int32)
+    w = np.zeros(Q)
+    o = np.zeros(Q, np.int32)
+    lib().ora_lattice(e.ctypes.data_as(_ip), _d(w), o.ctypes.data_as(_ip))
+    return e, w, o
+
+
+def equilibria(n, eps, beta, c_l):
+    feq = np.zeros(Q)
+    geq = np.zeros(Q)
+    b = _f64(beta)
+    lib().ora_equilibria(float(n), float(eps), _d(b), float(c_l), _d(feq), _d(geq))
+    return feq, geq
+
+
+def invert(N, E, M):
+    out = np.zeros(5)
+    m = _f64(M)
+    ok = lib().ora_invert(float(N), float(E), _d(m), _d(out))
+    return out[0], out[1], out[2:5].copy(), bool(ok)
+
+
+def collide(pf, pg, tau, c_l):
+    pf, pg = _f64(pf), _f64(pg)
+    of = np.zeros(Q)
+    og = np.zeros(Q)
+    ok = lib().ora_collide(_d(pf), _d(pg), float(tau), float(c_l), _d(of), _d(og))
+    return of, og, bool(ok)
+
+
+def init(p: Problem, n0, e0, beta0) -> np.ndarray:
+    """S_0 ([2][19][cells]) from initial fields n0, e0 [cells], beta0 [3][cells]."""
+    args, _ = p._args()
+    n0, e0, beta0 = _f64(n0).reshape(-1), _f64(e0).reshape(-1), _f64(beta0).reshape(3, -1)
+    S = np.zeros((2, Q, p.cells))
+    lib().ora_init(*args, _d(n0), _d(e0), _d(np.ascontiguousarray(beta0)), _d(S))
+    return S
+
+
+def run(p: Problem, S: np.ndarray, nsteps: int) -> int:
+    """Advance S ([2][19][cells], in place) by nsteps; returns the unphysical-update count."""
+    args, tau = p._args()
+    assert S.shape == (2, Q, p.cells) and S.dtype == np.float64 and S.flags.c_contiguous
+    return int(lib().ora_run(*args, _d(tau), _d(S), int(nsteps)))
+
+
+def run_g(p: Problem, Sg: np.ndarray, nsteps: int) -> int:
+    args, tau = p._args()
+    assert Sg.shape == (Q, p.cells) and Sg.flags.c_contiguous
+    return int(lib().ora_run_g(*args, _d(tau), _d(Sg), int(nsteps)))
+
+
+def update_cells(p: Problem, S: np.ndarray, idx) -> np.ndarray:
+    """One step evaluated at the given linear cell indices: returns [k][38] (f then g)."""
+    args, tau = p._args()
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    out = np.zeros((idx.size, 2 * Q))
+    lib().ora_update_cells(*args, _d(tau), _d(S), ctypes.c_long(idx.size),
+                           idx.ctypes.data_as(_lp), _d(out))
+    return out
+
+
+def moments(p: Problem, S: np.ndarray):
+    """(n, e, beta[3][cells], sums[batch][5]) of a stored state."""
+    dims = np.array([p.nx, p.ny, p.nz, p.batch], dtype=np.int32)
+    solid = None if p.solid is None else np.ascontiguousarray(p.solid.reshape(-1).astype(np.uint8))
+    n = np.zeros(p.cells)
+    e = np.zeros(p.cells)
+    b = np.zeros((3, p.cells))
+    sums = np.zeros((p.batch, 5))
+    lib().ora_moments(dims.ctypes.data_as(_ip), float(p.c_l),
+                      solid.ctypes.data_as(_u8p) if solid is not None else None,
+                      _d(S), _d(n), _d(e), _d(b), _d(sums))
+    return n, e, b, sums
+
+
+def adjoint_step(p: Problem, Sg, lam_next):
+    """One g-only reverse step; returns (lam_t, dL/dtau[batch], dL/dbeta_in[3], dL/de_in)."""
+    args, tau = p._args()
+    Sg, lam_next = _f64(Sg), _f64(lam_next)
+    lam_out = np.zeros((Q, p.cells))
+    dtau = np.zeros(p.batch)
+    dbin = np.zeros(3)
+    dein = np.zeros(1)
+    lib().ora_adjoint_step(*args, _d(tau), _d(Sg), _d(lam_next), _d(lam_out), _d(dtau),
+                           _d(dbin), _d(dein))
+    return lam_out, dtau, dbin, dein[0]
+
+
+def moments_adjoint(p: Problem, Sg, dLde, dLdb):
+    dims = np.array([p.nx, p.ny, p.nz, p.batch], dtype=np.int32)
+    solid = None if p.solid is None else np.ascontiguousarray(p.solid.reshape(-1).astype(np.uint8))
+    Sg, dLde, dLdb = _f64(Sg), _f64(dLde).reshape(-1), _f64(dLdb).reshape(3, -1)
+    lam = np.zeros((Q, p.cells))
+    lib().ora_moments_adjoint(dims.ctypes.data_as(_ip), float(p.c_l),
+                              solid.ctypes.data_as(_u8p) if solid is not None else None,
+                              _d(Sg), _d(dLde), _d(np.ascontiguousarray(dLdb)), _d(lam))
+    return lam
+
+
+def init_adjoint(p: Problem, e0, beta0, lam0):
+    args, _ = p._args()
+    e0, beta0, lam0 = _f64(e0).reshape(-1), _f64(beta0).reshape(3, -1), _f64(lam0)
+    de0 = np.zeros(p.cells)
+    db0 = np.zeros((3, p.cells))
+    dbin = np.zeros(3)
+    dein = np.zeros(1)
+    lib().ora_init_adjoint(*args, _d(e0), _d(np.ascontiguousarray(beta0)), _d(lam0), _d(de0),
+                           _d(db0), _d(dbin), _d(dein))
+    return de0, db0, dbin, dein[0]
+
+
+@dataclass
+class Loss:
+    """L = sum a (e - t)^2 + sum be*e + sum bb.beta over non-solid cells."""
+
+    a: Optional[np.ndarray] = None
+    t: Optional[np.ndarray] = None
+    be: Optional[np.ndarray] = None
+    bb: Optional[np.ndarray] = None  # [3][cells]
+
+    def ptrs(self):
+        self._keep = [_f64(v).reshape(-1) if v is not None else None
+                      for v in (self.a, self.t, self.be, self.bb)]
+        return [_d(v) if v is not None else None for v in self._keep]
+
+
+def loss(p: Problem, e0, beta0, nsteps, L: Loss) -> float:
+    args, tau = p._args()
+    e0, beta0 = _f64(e0).reshape(-1), np.ascontiguousarray(_f64(beta0).reshape(3, -1))
+    return float(lib().ora_loss(*args, _d(tau), _d(e0), _d(beta0), int(nsteps), *L.ptrs()))
+
+
+def loss_cs(p: Problem, e0, beta0, nsteps, L: Loss, d_tau=None, d_inflow=None, d_e0=None,
+            d_beta0=None):
+    """Complex-step directional derivative dL.d; returns (L, dL.d)."""
+    args, tau = p._args()
+    e0, beta0 = _f64(e0).reshape(-1), np.ascontiguousarray(_f64(beta0).reshape(3, -1))
+    dt, di, de, db = (_f64(v).reshape(-1) if v is not None else None
+                      for v in (d_tau, d_inflow, d_e0, d_beta0))
+    lv = np.zeros(1)
+    r = lib().ora_loss_cs(*args, _d(tau), _d(e0), _d(beta0), int(nsteps), *L.ptrs(),
+                          _d(dt), _d(di), _d(de), _d(db), _d(lv))
+    return float(lv[0]), float(r)
+
+
+@dataclass
+class Gradient:
+    loss: float
+    tau: np.ndarray
+    e_in: float
+    beta_in: np.ndarray
+    e0: np.ndarray
+    beta0: np.ndarray
+
+
+def gradient(p: Problem, e0, beta0, nsteps, L: Loss) -> Gradient:
+    """Store-all FP64 reverse sweep of a g-only run (oracle's own adjoint)."""
+    args, tau = p._args()
+    e0, beta0 = _f64(e0).reshape(-1), np.ascontiguousarray(_f64(beta0).reshape(3, -1))
+    gt = np.zeros(p.batch)
+    gi = np.zeros(4)
+    ge = np.zeros(p.cells)
+    gb = np.zeros((3, p.cells))
+    lv = lib().ora_gradient(*args, _d(tau), _d(e0), _d(beta0), int(nsteps), *L.ptrs(),
+                            _d(gt), _d(gi), _d(ge), _d(gb))
+    return Gradient(float(lv), gt, float(gi[0]), gi[1:4].copy(), ge, gb)

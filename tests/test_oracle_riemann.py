@@ -1,0 +1,108 @@
+"""The exact ideal Riemann solution, and the oracle's convergence toward it.
+
+The solver (oracle/riemann.py) is pinned by conservation laws it does not use
+directly: the Rankine-Hugoniot flux balance of T^{00}, T^{0z}, N^0 across its
+shock (it solves with Taub's velocity formula), and the global balance of the
+whole self-similar profile (fan, contact, shock) against the boundary fluxes.
+Then the oracle's shock tube must approach it as the paper's comparison does.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import rlb_inputs as ri
+from oracle import riemann
+from test_oracle_pins import golden, problem
+
+
+def conserved(e, b, n):
+    P = e / 3.0
+    g2 = 1.0 / (1.0 - b * b)
+    W = (e + P) * g2
+    # densities (T^00, T^0z, N^0) and fluxes (T^0z, T^zz, N^z)
+    U = np.array([W - P, W * b, n * np.sqrt(g2)])
+    F = np.array([W * b, W * b * b + P, n * np.sqrt(g2) * b])
+    return U, F
+
+
+@pytest.mark.parametrize("ratio", [16.0, 1.0 / 0.40999, 4.0, 30.0, 1.01])
+def test_shock_satisfies_rankine_hugoniot(ratio):
+    st = riemann.solve(1.0, 1.0 / ratio)
+    Us, Fs = conserved(st.e_star, st.beta_star, st.n_star_R)
+    UR, FR = conserved(st.e_R, 0.0, st.n_R)
+    assert np.allclose(Fs - FR, st.v_shock * (Us - UR), rtol=1e-12, atol=1e-14)
+    # rarefaction invariant between left and star states
+    J = lambda e, b: math.atanh(b) + math.sqrt(3.0) / 4.0 * math.log(e)
+    assert J(st.e_star, st.beta_star) == pytest.approx(J(1.0, 0.0), abs=1e-13)
+    assert 0 < st.beta_star < st.v_shock < 1
+
+
+def test_profile_global_balance():
+    """Integrals of the exact profile obey d/dt int U = F(left end) - F(right end)."""
+    st = riemann.solve(1.0, 1.0 / 16.0)
+    t = 1.0
+    xi = np.linspace(-1.0, 1.0, 400001)
+    e, b, n = riemann.profile(st, xi)
+    U, _ = conserved(e, b, n)
+    U0, F0 = conserved(np.where(xi < 0, st.e_L, st.e_R), 0 * xi, np.where(xi < 0, st.n_L, st.n_R))
+    dx = xi[1] - xi[0]
+    dU = ((U - U0)[:, 1:] + (U - U0)[:, :-1]).sum(1) * dx / 2
+    want = t * (F0[:, 0] - F0[:, -1])
+    assert np.allclose(dU, want, atol=2e-5)
+
+
+def test_weak_shock_moves_at_sound_speed():
+    st = riemann.solve(1.0, 1.0 / 1.0001)
+    assert st.v_shock == pytest.approx(1.0 / math.sqrt(3.0), rel=1e-4)
+
+
+def test_paper_pressure_ratio_gives_beta_about_0p2():
+    g = golden()
+    st = riemann.solve(g["P0_lattice"], g["P1_lattice"])
+    assert abs(st.beta_star - g["beta_shock_tube"]) < 0.02
+
+
+def _lb_tube(nz, steps, ratio, tau):
+    s = ri.shock_tube(nz=nz, e_L=1.0, e_R=1.0 / ratio, tau=tau, steps=steps)
+    p = problem(s)
+    S = oracle.init(p, s.n0, s.e0, s.beta0)
+    oracle.run(p, S, steps)
+    n, e, b, _ = oracle.moments(p, S)
+    return n, e, b[2]
+
+
+def _l1(a, b):
+    return np.abs(a - b).sum() / np.abs(b).sum()
+
+
+def test_shock_tube_converges_to_riemann_solution():
+    """1 x 1 x 800, e_L/e_R = 16, tau = 0.6, 500 steps: the plateau holds the exact
+    star state and the profile is within 0.5% (L1) of the ideal solution; halving
+    the resolution roughly doubles the error (the viscous layers scale with the
+    grid)."""
+    st = riemann.solve(1.0, 1.0 / 16.0)
+    n, e, b = _lb_tube(800, 500, 16.0, 0.6)
+    ee, be, _ = riemann.lattice_profile(st, 800, 500.0)
+    assert e[600] == pytest.approx(st.e_star, rel=1e-3)
+    assert b[600] == pytest.approx(st.beta_star, rel=1e-3)
+    err800 = _l1(e, ee)
+    assert err800 < 5e-3
+    assert _l1(b, be) < 5e-3
+    _, e4, _ = _lb_tube(400, 250, 16.0, 0.6)
+    ee4, _, _ = riemann.lattice_profile(st, 400, 250.0)
+    assert _l1(e4, ee4) / err800 > 1.5
+
+
+def test_paper_case_tube_converges():
+    """The paper's pressure ratio P1/P0, 1 x 1 x 800, 400 steps (3.2 fm/c): f stays
+    positive (beta* < c_l/3), and e, beta and n are within 0.5% of the ideal solution."""
+    g = golden()
+    ratio = g["P0_lattice"] / g["P1_lattice"]
+    st = riemann.solve(1.0, 1.0 / ratio)
+    n, e, b = _lb_tube(800, 400, ratio, 0.55)
+    ee, be, ne = riemann.lattice_profile(st, 800, 400.0)
+    assert _l1(e, ee) < 5e-3
+    assert _l1(n, ne) < 5e-3
+    assert np.all(np.isfinite(n)) and n.min() > 0
