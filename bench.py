@@ -1,0 +1,260 @@
+"""Benchmark of the RLB stream-collide step on one MI355X.
+
+Default workload: the 200 x 100 x 100 relativistic shock on a sphere (FP64
+populations, |beta_in| = 0.5, tau = 0.55), the set-up of the paper's 3-D
+demonstration.  A step is one pass of the whole hot path (pull streaming with
+inflow / outflow / bounce-back resolution, moments, FP64 inversion, equilibria,
+BGK relaxation of f and g) over the lattice; inputs are resident in HBM before
+the timed region.
+
+Prints ONE JSON line with MLUPS (all lattice cells), the HBM roofline of the
+step kernel, the FP64 oracle timed on the host (bounded sample) and extra
+measurements: mixed-precision storage speed-ups on the 256^3 periodic box and
+the adjoint / forward step-time ratio.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+Q = 19
+
+
+def algorithmic_bytes(s, elem: int, with_f: bool = True) -> dict:
+    """Bytes one step must move: every updated (non-solid, non-inflow) cell reads
+    and writes 19 values per population; inflow cells write them only; each cell
+    reads its 1-byte class when an obstacle mask is present."""
+    cells = s.cells
+    solid = 0 if s.solid is None else int(s.solid.sum())
+    inflow = 0
+    if any(b == 2 for ax in s.bc for b in ax):
+        for a, (lo, hi) in enumerate(s.bc):
+            n = (s.nx, s.ny, s.nz)
+            area = cells // n[a]
+            if lo == 2 or hi == 2:
+                plane = np.zeros(cells, bool).reshape(s.batch, s.nz, s.ny, s.nx)
+                sl = [slice(None)] * 4
+                sl[3 - a] = 0 if lo == 2 else n[a] - 1
+                plane[tuple(sl)] = True
+                plane = plane.reshape(-1)
+                if s.solid is not None:
+                    plane &= s.solid.reshape(-1) == 0
+                inflow = int(plane.sum())
+    upd = cells - solid - inflow
+    pops = 2 if with_f else 1
+    per_upd = pops * Q * 2 * elem
+    b = upd * per_upd + inflow * pops * Q * elem + (cells if s.solid is not None else 0)
+    return {"bytes": b, "updated_cells": upd, "inflow_cells": inflow, "solid_cells": solid,
+            "bytes_per_updated_cell": per_upd}
+
+
+def time_steps(fn, steps: int, stream) -> float:
+    import torch
+
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    fn(steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3  # seconds
+
+
+def copy_probe(nbytes: int = 4 << 30, reps: int = 10) -> float:
+    """Device copy bandwidth (GB/s, read + write) with an elementwise kernel; also
+    the calibration kernel of known traffic for the hardware byte counters."""
+    import torch
+
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        torch.neg(x, out=y)
+    e.record()
+    torch.cuda.synchronize()
+    dt = s.elapsed_time(e) / 1e3 / reps
+    del x, y
+    return 2 * nbytes / dt / 1e9
+
+
+def cpu_baseline(s, seconds: float = 12.0) -> dict:
+    """The FP64 oracle (single-threaded C++, test infrastructure) on a bounded
+    sample of the same workload: full lattice, as many steps as fit ~seconds."""
+    import oracle
+
+    p = oracle.Problem(s.nx, s.ny, s.nz, s.batch, s.c_l, s.bc, s.inflow, s.tau, s.solid)
+    S = oracle.init(p, s.n0, s.e0, s.beta0)
+    t0 = time.perf_counter()
+    oracle.run(p, S, 1)
+    one = time.perf_counter() - t0
+    steps = max(1, int(seconds / max(one, 1e-9)) - 1)
+    t0 = time.perf_counter()
+    oracle.run(p, S, steps)
+    dt = time.perf_counter() - t0
+    total_steps = steps
+    mlups = s.cells * total_steps / dt / 1e6
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{s.nx}x{s.ny}x{s.nz} sphere lattice, {total_steps} steps "
+                      f"({dt:.1f} s, FP64 single-threaded C++ oracle, host: {cpu}, "
+                      f"nproc {os.cpu_count()})"}
+
+
+def bench_forward(s, steps, warmup):
+    import torch
+
+    from paper_0912_2913_amd.solver import Solver
+
+    sv = Solver(s)
+    sv.step(warmup)
+    dt = time_steps(sv.step, steps, sv.stream)
+    counts = sv.counters()
+    sv.close()
+    del sv
+    torch.cuda.empty_cache()
+    return dt, counts
+
+
+def bench_adjoint(s, steps, warmup):
+    """Per-step reverse-sweep cost: recompute of the g state (one g-only step)
+    plus one adjoint step, against one forward f+g step."""
+    import torch
+
+    from paper_0912_2913_amd.solver import Solver
+
+    sv = Solver(s)
+    sv.step(warmup)
+    fwd = time_steps(sv.step, steps, sv.stream)
+    g = [sv.g_state().clone(), sv.new_g()]
+    lam = [sv.new_lam().zero_(), sv.new_lam().zero_()]
+    lam[0][:, : sv.cells] = 1e-3
+    dtau = torch.zeros(sv.batch, dtype=torch.float64, device=sv.device)
+    dbi = torch.zeros(3, dtype=torch.float64, device=sv.device)
+    dei = torch.zeros(1, dtype=torch.float64, device=sv.device)
+
+    def recompute(n):
+        for i in range(n):
+            sv.step_g(g[i % 2], g[(i + 1) % 2])
+
+    def adjoint(n):
+        for i in range(n):
+            sv.adjoint_step(g[0], lam[i % 2], lam[(i + 1) % 2], dtau, dbi, dei)
+
+    def both(n):
+        for i in range(n):
+            sv.step_g(g[0], g[1])
+            sv.adjoint_step(g[0], lam[i % 2], lam[(i + 1) % 2], dtau, dbi, dei)
+
+    recompute(2)
+    adjoint(2)
+    t_re = time_steps(recompute, steps, sv.stream)
+    t_adj = time_steps(adjoint, steps, sv.stream)
+    t_both = time_steps(both, steps, sv.stream)
+    sv.close()
+    del sv, g, lam
+    torch.cuda.empty_cache()
+    return {"forward_ms": 1e3 * fwd / steps, "recompute_g_ms": 1e3 * t_re / steps,
+            "adjoint_ms": 1e3 * t_adj / steps, "recompute_plus_adjoint_ms": 1e3 * t_both / steps,
+            "ratio": t_both / fwd, "adjoint_kernel_ratio": t_adj / fwd}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run the calibration copy kernel (for counter runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the stream-collide step is not run across "
+              "GPUs (the multi-GPU z-slab decomposition is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import rlb_inputs as ri
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    s = ri.sphere()
+    ab = algorithmic_bytes(s, 8)
+    dt, counts = bench_forward(s, args.steps, args.warmup)
+    ms = 1e3 * dt / args.steps
+    mlups = s.cells * args.steps / dt / 1e6
+    achieved = ab["bytes"] / (dt / args.steps) / 1e9
+    out = {
+        "metric": "MLUPS (f+g D3Q19, 1 GPU) & %HBM roofline; adjoint/forward step time ratio",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "sphere shock 200x100x100 D3Q19 f+g, FP64 populations, sphere r=15 "
+                               "bounce-back, inflow |beta|=0.5, outflow, tau=0.55",
+                   "cells": s.cells, "fluid_updated_cells": ab["updated_cells"],
+                   "fluid_mlups": round(ab["updated_cells"] * args.steps / dt / 1e6, 2),
+                   "unphysical_g_updates": counts[0], "nonpositive_f_eq_updates": counts[1]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step<F64,f+g>",
+                     "bytes_per_launch": ab["bytes"]},
+    }
+    if args.copy_probe:
+        out["copy_probe_GBs"] = round(copy_probe(), 1)
+    if not args.no_extras:
+        extras = {}
+        # mixed-precision storage on the 256^3 periodic box (same step kernel family)
+        box_steps = 100
+        t64 = None
+        for st in (ri.F64, ri.F32, ri.F32DEV, ri.F16DEV, ri.BF16DEV):
+            b = ri.periodic_box(storage=st)
+            el = {ri.F64: 8, ri.F32: 4, ri.F32DEV: 4, ri.F16DEV: 2, ri.BF16DEV: 2}[st]
+            dtb, _ = bench_forward(b, box_steps, 5)
+            if st == ri.F64:
+                t64 = dtb
+            gbs = b.cells * 2 * Q * 2 * el / (dtb / box_steps) / 1e9
+            extras[ri.STORAGE_NAMES[st]] = {"mlups": round(b.cells * box_steps / dtb / 1e6, 1),
+                                            "ms_per_step": round(1e3 * dtb / box_steps, 4),
+                                            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                            "speedup_vs_f64": round(t64 / dtb, 3)}
+            del b
+        out["mixed_precision_256cube"] = extras
+        out["adjoint_sphere_f64"] = {k: round(v, 4) for k, v in
+                                     bench_adjoint(s, min(args.steps, 200), 5).items()}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * rlb.h -- C ABI of the MI355X relativistic lattice Boltzmann (RLB) library.
+ *
+ * The library advances the two-population D3Q19 scheme of Mendoza, Boghosian,
+ * Herrmann and Succi, "Lattice Boltzmann scheme for relativistic fluids"
+ * (arXiv:0912.2913): a number population f_i and an energy-momentum
+ * population g_i per cell and velocity, relaxed by one BGK time tau
+ * (eqs. lbe1, lbe2) toward the ultra-relativistic equilibria
+ * (eqs. equil1s, equil2as, equil2bs), with (n, e, beta) recovered from the
+ * macroscopic constraints n gamma = sum f_i, (e+P) gamma^2 - P = sum g_i,
+ * (e+P) gamma^2 beta = sum g_i c_i closed by e = 3P.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Units: c = 1; c_i = c_l e_i with e_i the integer D3Q19 vectors; one cell
+ *    = dx, one step = dt = dx / c_l; tau is in units of dt (omega = 1/tau).
+ *  - Cell index: cell = ((b*nz + z)*ny + y)*nx + x, x fastest; b = instance.
+ *    cells = batch*nz*ny*nx.
+ *  - Population buffer ("state"): [pop][q][q_stride] elements, pop 0 = f,
+ *    pop 1 = g, q = 0..18, q_stride = cells rounded up to a multiple of 64
+ *    (see rlb_buffer_layout).  A "g block" is the [19][q_stride] second half.
+ *    Element type by storage: RLB_F64 double; RLB_F32 float; RLB_F32DEV float,
+ *    RLB_F16DEV IEEE binary16, RLB_BF16DEV bfloat16, the *DEV forms holding
+ *    the deviation S_i - R_i from the rest equilibrium R at (n_ref, e_ref).
+ *  - Velocity ordering: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..10 = (1,1,0),
+ *    (-1,-1,0),(1,-1,0),(-1,1,0); 11..14 = (1,0,1),(-1,0,-1),(1,0,-1),
+ *    (-1,0,1); 15..18 = (0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1).
+ *  - Stored state = post-collision populations S_t; one step computes
+ *    S_{t+1}(x) = collide(pull(S_t))(x).  Fields at time t are the moments of
+ *    S_t (the collision conserves sum f, sum g and sum g c_i).
+ *  - Boundaries (per face): PERIODIC wraps; OUTFLOW copies (pull source
+ *    clamped into the domain); INFLOW holds the face plane at the equilibrium
+ *    of (inflow_n, inflow_e, inflow_beta).  Solid cells reflect by half-way
+ *    bounce-back and are never updated.
+ *  - Adjoint buffers ("lambda"): [19][q_stride], double for RLB_F64 storage,
+ *    float for every other storage.
+ *  - Device pointers address memory on the solver's device; every call that
+ *    launches work is asynchronous on the stream given to rlb_init unless its
+ *    comment says it synchronises.  Nothing throws across the ABI.
+ *  - Errors: RLB_EINVAL = invalid argument, nothing launched;
+ *    RLB_EDEVICE = a HIP call failed; rlb_last_error() gives details.
+ */
+#ifndef RLB_H
+#define RLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rlb_solver rlb_solver; /* opaque, owned by the library */
+
+typedef enum {
+  RLB_OK = 0,
+  RLB_EINVAL = -1,
+  RLB_ENOMEM = -2,
+  RLB_EDEVICE = -3,
+  RLB_EUNPHYSICAL = -4
+} rlb_status;
+
+typedef enum { RLB_BC_PERIODIC = 0, RLB_BC_OUTFLOW = 1, RLB_BC_INFLOW = 2 } rlb_bc;
+
+typedef enum {
+  RLB_F64 = 0,
+  RLB_F32 = 1,
+  RLB_F32DEV = 2,
+  RLB_F16DEV = 3,
+  RLB_BF16DEV = 4
+} rlb_storage;
+
+/* Problem statement (shock-tube and obstacle sections of the paper: domain,
+ * lattice speed c_l, fixed obstacle, inflow state; e = 3P is built in). */
+typedef struct {
+  int32_t nx, ny, nz, batch; /* extents (>= 1); batch independent lattices       */
+  double c_l;                /* lattice speed in units of c (> 0)                */
+  int32_t bc[3][2];          /* [axis x,y,z][low, high face] : rlb_bc            */
+  double inflow_n, inflow_e; /* inflow state (used when a face is INFLOW)        */
+  double inflow_beta[3];
+  int32_t storage;           /* rlb_storage                                      */
+  double n_ref, e_ref;       /* rest reference of the *DEV storages              */
+} rlb_params;
+
+/* Layout of one population buffer for these parameters: q_stride elements per
+ * direction and the byte size of a full f+g buffer (2*19*q_stride*elem).
+ * Either output may be NULL.  Host-only, no device work. */
+rlb_status rlb_buffer_layout(const rlb_params *p, int64_t *q_stride, int64_t *state_bytes);
+
+/* Create a solver and write the initial state S_0 into pop_a.
+ *  tau   : host [batch], each > 1/2 (eta = (4/9) gamma^2 e (tau - dt/2) c_l^2 > 0).
+ *  solid : device uint8 [cells] (nonzero = solid) or NULL; copied.
+ *  n0, e0: device double [cells]; beta0: device double [3][cells].  Read
+ *          during this call only.  S_0 = (f^eq(n0 gamma0, beta0),
+ *          g^eq(e0, beta0)) on fluid cells, the inflow equilibrium on inflow
+ *          cells, zeros on solid cells (in both pop_a and pop_b).
+ *  pop_a, pop_b: caller-owned device buffers of state_bytes each, aliased by
+ *          the solver until rlb_destroy; the steps ping-pong between them.
+ *  stream: hipStream_t (NULL = default stream) for all of the solver's work.
+ * Validation: extents >= 1 (>= 2 on non-periodic axes); periodic on both or
+ * neither face of an axis; at most one INFLOW face; inflow_e > 0 and
+ * |inflow_beta| < 1 when a face is INFLOW; c_l > 0; e_ref > 0 for *DEV;
+ * cells <= 2^31 - 64.  Library-owned device memory: a copy of tau, a cell
+ * class mask, small reduction and counter buffers. */
+rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
+                    const uint8_t *solid, const double *n0, const double *e0,
+                    const double *beta0, void *pop_a, void *pop_b, void *stream);
+
+/* Advance nsteps (>= 0) full f+g steps (eqs. lbe1 and lbe2 with pull
+ * streaming and the boundary rules above).  Asynchronous. */
+rlb_status rlb_step(rlb_solver *h, int32_t nsteps);
+
+/* One step of the g population alone from g_src to g_dst (g blocks,
+ * [19][q_stride], distinct).  f never enters (e, beta), so this is the exact
+ * g part of rlb_step; used to recompute states in a reverse sweep. */
+rlb_status rlb_step_g(rlb_solver *h, const void *g_src, void *g_dst);
+
+/* Device pointer of the buffer that holds the current state S_t. */
+rlb_status rlb_current(rlb_solver *h, void **state);
+
+/* Fields of the current state: n, e [cells], beta [3][cells] (device double,
+ * any may be NULL; zeros on solid cells).  sums: host double [batch][5] =
+ * (sum f, sum g, sum g c_x, sum g c_y, sum g c_z) over non-solid cells,
+ * reduced in a fixed order in FP64 (bitwise reproducible), or NULL.  With
+ * sums != NULL the call synchronises the stream. */
+rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double *sums);
+
+/* Counters of the steps run since the last call (synchronises): counts[0] =
+ * unphysical g updates (4E^2 - 3|M|^2 <= 0, e <= 0, |beta| >= 1 or NaN);
+ * counts[1] = f updates whose equilibrium had a non-positive component
+ * (some c_i.beta <= -c_l^2/3, the paper's positivity bound).  Resets both.
+ * Returns RLB_EUNPHYSICAL when counts[0] > 0. */
+rlb_status rlb_counters(rlb_solver *h, int64_t counts[2]);
+
+/* One reverse step of the g population:
+ *   lam_out = (d S_{t+1} / d S_t)^T lam_next,
+ * where S_{t+1} = step(S_t) with S_t = g_state_t (a g block).  lam_out is
+ * overwritten; lam_next is not modified.  Also accumulates (+=, device
+ * double): dL_dtau[batch] += lam_next . d S_{t+1} / d tau;
+ * dL_dbeta_in[3], dL_de_in[1] += lam_next . d S_{t+1} / d(inflow state).
+ * Any gradient pointer may be NULL.  Partial sums are reduced in a fixed
+ * order, so results are bitwise reproducible. */
+rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *lam_next,
+                            void *lam_out, double *dL_dtau, double *dL_dbeta_in,
+                            double *dL_de_in);
+
+/* Seed of a reverse sweep: lam_T = (d(e, beta) / d S_T)^T (dL_de, dL_dbeta)
+ * per cell, with (e, beta) the fields of the g block g_state_T.  dL_de
+ * [cells], dL_dbeta [3][cells]: device double.  lam_T is overwritten. */
+rlb_status rlb_moments_adjoint(rlb_solver *h, const void *g_state_T, const double *dL_de,
+                               const double *dL_dbeta, void *lam_T);
+
+/* End of a reverse sweep: S_0 = g^eq(e0, beta0) (and the inflow state on
+ * inflow cells), so dL_de0 [cells] and dL_dbeta0 [3][cells] are overwritten
+ * with (d S_0 / d(e0, beta0))^T lam_0, and dL_dbeta_in, dL_de_in accumulate
+ * the inflow cells' share.  e0, beta0: the initial fields given to rlb_init
+ * (device double). */
+rlb_status rlb_init_adjoint(rlb_solver *h, const double *e0, const double *beta0,
+                            const void *lam_0, double *dL_de0, double *dL_dbeta0,
+                            double *dL_dbeta_in, double *dL_de_in);
+
+/* Release the solver's own memory (not pop_a / pop_b).  Synchronises. */
+rlb_status rlb_destroy(rlb_solver *h);
+
+const char *rlb_status_string(rlb_status s);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *rlb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLB_H */

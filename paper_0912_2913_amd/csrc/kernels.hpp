@@ -1,0 +1,923 @@
+// Kernels of the RLB step for gfx950 (MI355X).
+//
+// One thread updates one cell; a 64-lane wavefront covers 64 consecutive cells
+// of the x-fastest linear index, so each of the 38 pulls of a wavefront is one
+// contiguous 64-element read shifted by the streaming offset, and each of the
+// 38 stores is one contiguous 64-element write (SoA [pop][q][cell]).  The
+// update is a streaming, bandwidth-bound stencil (about 0.5 flop per byte in
+// FP64): it is not a dense contraction, so no MFMA is used.  Workgroups are
+// remapped so that each XCD (own L2) works on one contiguous slab of cells,
+// which keeps the cache lines shared by neighbouring workgroups (the +-1 x
+// shifts) inside one L2.
+//
+// Physics (eqs. lbe1/lbe2, equil1s/equil2as/equil2bs, the macroscopic
+// constraints closed by e = 3P), in the form evaluated here:
+//   E = sum g_i, M = c_l sum g_i e_i, N = sum f_i;
+//   D = sqrt(4E^2 - 3|M|^2), e = D - E, W = (e+P) gamma^2 = (2E + D)/3,
+//   beta = M / W   (the rest-continuous root of 3W^2 - 4EW + |M|^2 = 0);
+//   with b_i = e_i.beta / c_l and s = (3/2)|beta|^2 / c_l^2:
+//   g_i^eq = w_i [ e / c_l^2 + W (3 b_i + (9/2) b_i^2 - s) ]          (i > 0)
+//   g_0^eq = w_0 [ e (3 - 2/c_l^2) + W (3 |beta|^2 - s) ]
+//   f_i^eq = w_i N (1 + 3 b_i)
+//   S' = pre + (1/tau)(eq - pre).
+// These equal the paper's equilibria on the physical manifold
+// (W = (4/3) e gamma^2, e gamma^2 / (gamma^2 c_l^2) = e / c_l^2, and
+// 3W - 4e = 3 W |beta|^2), without the 1/(1 - beta^2) division.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "codec.hpp"
+#include "lattice.hpp"
+
+namespace rlb {
+
+constexpr int BLOCK = 256;
+constexpr uint8_t CLS_SOLID = 1;
+constexpr uint8_t CLS_NEAR = 2;  // some resolved neighbour is solid
+
+// Division by a runtime constant via multiply-high (valid for n < 2^31).
+struct FastDiv {
+  uint32_t d, m, s;
+};
+
+__device__ __forceinline__ uint32_t fdiv(const FastDiv &f, uint32_t n) {
+  return (__umulhi(n, f.m) + n) >> f.s;
+}
+
+struct Geom {
+  int n[3];  // nx, ny, nz
+  int batch;
+  int per;  // cells per instance
+  int nblk_per, nblk;
+  long long qs;  // elements per direction slice (cells rounded up to 64)
+  FastDiv div_x, div_y, div_blk;
+  int periodic[3];
+  int inflow_lo[3], inflow_hi[3];
+  int any_inflow;
+  int off[Q];          // fast-path pull offsets (source = cell - off[q])
+  int flo[3], fhi[3];  // forward fast range per axis
+  int alo[3], ahi[3];  // adjoint fast range per axis
+};
+
+struct Phys {
+  double c, inv_c, inv_c2, k0;  // k0 = 3 - 2/c_l^2
+  double n_ref, e_ref;          // zero unless the storage holds deviations
+  const double *omega;          // [batch] 1/tau
+  const uint8_t *cls;           // [cells] class bits, or null (no obstacle)
+};
+
+// Inflow state for the adjoint of the held face (e_in, beta_in).
+struct InflowState {
+  double e, bx, by, bz;
+};
+
+struct Cell {
+  int b, x, y, z, local, L;
+  long long idx;
+  bool active;
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs; give XCD k the k-th
+// contiguous range of logical blocks.
+__device__ __forceinline__ int xcd_remap(int B, int nblk) {
+  int per = nblk >> 3, rem = nblk & 7;
+  int k = B & 7, i = B >> 3;
+  return k * per + min(k, rem) + i;
+}
+
+__device__ __forceinline__ Cell decode_cell(const Geom &g) {
+  Cell c;
+  c.L = xcd_remap((int)blockIdx.x, g.nblk);
+  c.b = (int)fdiv(g.div_blk, (uint32_t)c.L);
+  c.local = (c.L - c.b * g.nblk_per) * BLOCK + (int)threadIdx.x;
+  c.active = c.local < g.per;
+  uint32_t t = fdiv(g.div_x, (uint32_t)c.local);
+  c.x = c.local - (int)t * g.n[0];
+  uint32_t z = fdiv(g.div_y, t);
+  c.y = (int)t - (int)z * g.n[1];
+  c.z = (int)z;
+  c.idx = (long long)c.b * g.per + c.local;
+  return c;
+}
+
+__device__ __forceinline__ bool is_inflow(const Geom &g, int x, int y, int z) {
+  if (!g.any_inflow) return false;
+  return (g.inflow_lo[0] && x == 0) || (g.inflow_hi[0] && x == g.n[0] - 1) ||
+         (g.inflow_lo[1] && y == 0) || (g.inflow_hi[1] && y == g.n[1] - 1) ||
+         (g.inflow_lo[2] && z == 0) || (g.inflow_hi[2] && z == g.n[2] - 1);
+}
+
+__device__ __forceinline__ bool in_fast(const Cell &c, const int lo[3], const int hi[3]) {
+  return c.x >= lo[0] && c.x <= hi[0] && c.y >= lo[1] && c.y <= hi[1] && c.z >= lo[2] &&
+         c.z <= hi[2];
+}
+
+// Pull-source coordinate on one axis: wrap (periodic) or clamp (outflow).
+__device__ __forceinline__ int resolve(const Geom &g, int a, int r, bool &clamped) {
+  const int n = g.n[a];
+  if (g.periodic[a]) {
+    if (r < 0) r += n;
+    if (r >= n) r -= n;
+    return r;
+  }
+  if (r < 0) {
+    clamped = true;
+    return 0;
+  }
+  if (r >= n) {
+    clamped = true;
+    return n - 1;
+  }
+  return r;
+}
+
+__device__ __forceinline__ long long cell_index(const Geom &g, int b, int x, int y, int z) {
+  return (long long)b * g.per + ((long long)z * g.n[1] + y) * g.n[0] + x;
+}
+
+__device__ __forceinline__ bool solid_at(const Phys &ph, long long i) {
+  return ph.cls != nullptr && (ph.cls[i] & CLS_SOLID);
+}
+
+// General pull of direction q at cell c: source cell and direction
+// (bounce-back off a solid source returns the cell's own opposite population).
+struct Pull {
+  long long idx;
+  int q;
+  bool clamped;  // source clamped into the domain on some axis
+  bool bounce;
+};
+
+__device__ __forceinline__ Pull pull_general(const Geom &g, const Phys &ph, const Cell &c, int q) {
+  Pull p;
+  p.clamped = false;
+  int sx = resolve(g, 0, c.x - EX[q], p.clamped);
+  int sy = resolve(g, 1, c.y - EY[q], p.clamped);
+  int sz = resolve(g, 2, c.z - EZ[q], p.clamped);
+  long long s = cell_index(g, c.b, sx, sy, sz);
+  p.bounce = solid_at(ph, s);
+  if (p.bounce) {
+    p.idx = c.idx;
+    p.q = OPP[q];
+  } else {
+    p.idx = s;
+    p.q = q;
+  }
+  return p;
+}
+
+// Momentum sum_i e_i v_i over mirror pairs: each direction with e_a = +1 is
+// differenced with its mirror image across the plane normal to axis a before
+// anything else is added.  A state symmetric under that mirror then gives
+// exactly zero momentum along a.  A sequential sum over i leaves a
+// rounding residual (~1e-17) whenever mirror pairs hold values of opposite
+// sign.  At high shock strengths the scheme is unstable to transverse
+// perturbations (1-D shock tubes at e_L/e_R = 16 amplify them ~20x per 10
+// steps), so that residual alone would seed a transverse blow-up of an
+// otherwise one-dimensional flow.
+template <class T>
+__device__ __forceinline__ void mirror_sums(const T (&v)[Q], T &mx, T &my, T &mz) {
+  mx = ((v[1] - v[2]) + (v[7] - v[10])) + ((v[9] - v[8]) + (v[11] - v[14])) + (v[13] - v[12]);
+  my = ((v[3] - v[4]) + (v[7] - v[9])) + ((v[10] - v[8]) + (v[15] - v[18])) + (v[17] - v[16]);
+  mz = ((v[5] - v[6]) + (v[11] - v[13])) + ((v[14] - v[12]) + (v[15] - v[17])) + (v[18] - v[16]);
+}
+
+// Result of the moment inversion (FP64).
+struct Inv {
+  double E, Mx, My, Mz, D, eps, W, bx, by, bz;
+  bool bad;
+};
+
+__device__ __forceinline__ Inv invert(double E, double Mx, double My, double Mz) {
+  Inv r;
+  r.E = E;
+  r.Mx = Mx;
+  r.My = My;
+  r.Mz = Mz;
+  double D2 = 4.0 * E * E - 3.0 * (Mx * Mx + My * My + Mz * Mz);
+  r.D = sqrt(D2);
+  r.eps = r.D - E;
+  r.W = (2.0 * E + r.D) * (1.0 / 3.0);
+  double iW = 1.0 / r.W;
+  r.bx = Mx * iW;
+  r.by = My * iW;
+  r.bz = Mz * iW;
+  double b2 = r.bx * r.bx + r.by * r.by + r.bz * r.bz;
+  r.bad = !(D2 > 0.0) || !(r.eps > 0.0) || !(b2 < 1.0);
+  return r;
+}
+
+// Equilibrium coefficients of one cell in the compute type T; eq() returns
+// the equilibrium minus the rest reference R (R = 0 for non-deviation
+// storage).
+template <class T>
+struct EqCoef {
+  T W, Ad, A0, bx, by, bz, s, N, Nd;
+};
+
+template <class T>
+__device__ __forceinline__ EqCoef<T> eq_coef(const Phys &ph, double N, double eps, double W,
+                                             double bx, double by, double bz) {
+  EqCoef<T> k;
+  double b2 = bx * bx + by * by + bz * bz;
+  double s = 1.5 * b2 * ph.inv_c2;
+  k.W = (T)W;
+  k.Ad = (T)((eps - ph.e_ref) * ph.inv_c2);
+  k.A0 = (T)((eps - ph.e_ref) * ph.k0 + W * (3.0 * b2 - s));
+  k.bx = (T)(bx * ph.inv_c);
+  k.by = (T)(by * ph.inv_c);
+  k.bz = (T)(bz * ph.inv_c);
+  k.s = (T)s;
+  k.N = (T)N;
+  k.Nd = (T)(N - ph.n_ref);
+  return k;
+}
+
+template <class T>
+__device__ __forceinline__ T dot_e(const EqCoef<T> &k, int q) {
+  // e_q . beta / c_l with e_q in {-1, 0, 1}^3 (folds to adds after unrolling)
+  T r = (T)0;
+  if (EX[q] == 1) r += k.bx;
+  if (EX[q] == -1) r -= k.bx;
+  if (EY[q] == 1) r += k.by;
+  if (EY[q] == -1) r -= k.by;
+  if (EZ[q] == 1) r += k.bz;
+  if (EZ[q] == -1) r -= k.bz;
+  return r;
+}
+
+template <class T>
+__device__ __forceinline__ T geq_dev(const EqCoef<T> &k, int q) {
+  if (q == 0) return (T)W0 * k.A0;
+  T b = dot_e(k, q);
+  return (T)WQ[q] * (k.Ad + k.W * (b * ((T)3 + (T)4.5 * b) - k.s));
+}
+
+template <class T>
+__device__ __forceinline__ T feq_dev(const EqCoef<T> &k, int q) {
+  if (q == 0) return (T)W0 * k.Nd;
+  T b = dot_e(k, q);
+  return (T)WQ[q] * (k.Nd + (T)3 * k.N * b);
+}
+
+// Rest reference R_q (deviation storage) in FP64.
+__device__ __forceinline__ double rest_g(const Phys &ph, int q) {
+  return q == 0 ? W0 * ph.e_ref * ph.k0 : WQ[q] * ph.e_ref * ph.inv_c2;
+}
+__device__ __forceinline__ double rest_f(const Phys &ph, int q) { return WQ[q] * ph.n_ref; }
+
+// Wave-level ballot counter.
+__device__ __forceinline__ void count_lanes(bool flag, unsigned long long *ctr) {
+  unsigned long long m = __ballot(flag);
+  if (m != 0ull) {
+    int lane = (int)(threadIdx.x & 63u);
+    if (lane == __ffsll((long long)m) - 1) atomicAdd(ctr, (unsigned long long)__popcll(m));
+  }
+}
+
+// Deterministic sum of K doubles over the workgroup; thread 0 gets the result.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double *out) {
+  __shared__ double red[BLOCK / 64][K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    v[k] = x;
+  }
+  const int wave = (int)threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[wave][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = red[0][k];
+      for (int w = 1; w < BLOCK / 64; ++w) s += red[w][k];
+      out[k] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward stream-collide step.  DO_F = false updates the g population only
+// (src/dst then address g blocks).
+template <int ST, bool DO_F>
+__global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
+                                                const typename Codec<ST>::elem *__restrict__ src,
+                                                typename Codec<ST>::elem *__restrict__ dst,
+                                                const typename Codec<ST>::elem *__restrict__ in_eq,
+                                                unsigned long long *__restrict__ counters) {
+  using Cd = Codec<ST>;
+  using T = typename Cd::calc;
+  using El = typename Cd::elem;
+  const Cell c = decode_cell(g);
+  if (!c.active) return;
+  const uint8_t cls = ph.cls ? ph.cls[c.idx] : (uint8_t)0;
+  if (cls & CLS_SOLID) return;
+  const size_t qs = (size_t)g.qs;
+  const El *__restrict__ gs = DO_F ? src + Q * qs : src;
+  El *__restrict__ gd = DO_F ? dst + Q * qs : dst;
+  if (is_inflow(g, c.x, c.y, c.z)) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      gd[q * qs + c.idx] = in_eq[Q + q];
+      if (DO_F) dst[q * qs + c.idx] = in_eq[q];
+    }
+    return;
+  }
+  T pg[Q], pf[Q];
+  if (!(cls & CLS_NEAR) && in_fast(c, g.flo, g.fhi)) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const long long s = c.idx - g.off[q];
+      pg[q] = Cd::dec(gs[q * qs + s]);
+      if (DO_F) pf[q] = Cd::dec(src[q * qs + s]);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const Pull p = pull_general(g, ph, c, q);
+      pg[q] = Cd::dec(gs[p.q * qs + p.idx]);
+      if (DO_F) pf[q] = Cd::dec(src[p.q * qs + p.idx]);
+    }
+  }
+  // moments (in T), inversion (FP64)
+  T sE = (T)0, sx, sy, sz;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) sE += pg[q];
+  mirror_sums(pg, sx, sy, sz);
+  const Inv iv = invert(ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
+                        ph.c * (double)sz);
+  double Nsum = 0.0;
+  T sN = (T)0;
+  if (DO_F) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) sN += pf[q];
+    Nsum = ph.n_ref + (double)sN;
+  }
+  const EqCoef<T> k = eq_coef<T>(ph, Nsum, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
+  const T om = (T)ph.omega[c.b];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const T post = pg[q] + om * (geq_dev(k, q) - pg[q]);
+    gd[q * qs + c.idx] = Cd::enc(post);
+  }
+  if (DO_F) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const T post = pf[q] + om * (feq_dev(k, q) - pf[q]);
+      dst[q * qs + c.idx] = Cd::enc(post);
+    }
+  }
+  count_lanes(iv.bad, &counters[0]);
+  if (DO_F) {
+    // f^eq_i >= 0 needs 1 + 3 b_i > 0 for every i; the largest |b_i| is on a
+    // diagonal: |b_x| + |b_y|, |b_x| + |b_z| or |b_y| + |b_z|.
+    const double ax = fabs(iv.bx), ay = fabs(iv.by), az = fabs(iv.bz);
+    const double mb = fmax(ax + ay, fmax(ax + az, ay + az)) * ph.inv_c;
+    count_lanes(!(3.0 * mb < 1.0), &counters[1]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: equilibria of (n0, e0, beta0); inflow cells take the inflow
+// equilibrium; solid cells hold zeros in both buffers.
+template <int ST>
+__global__ __launch_bounds__(BLOCK) void k_init(const Geom g, const Phys ph,
+                                                const double *__restrict__ n0,
+                                                const double *__restrict__ e0,
+                                                const double *__restrict__ beta0,
+                                                typename Codec<ST>::elem *__restrict__ pa,
+                                                typename Codec<ST>::elem *__restrict__ pb,
+                                                const typename Codec<ST>::elem *__restrict__ in_eq) {
+  using Cd = Codec<ST>;
+  using T = typename Cd::calc;
+  const Cell c = decode_cell(g);
+  if (!c.active) return;
+  const size_t qs = (size_t)g.qs;
+  const size_t cells = (size_t)g.batch * g.per;
+  if (solid_at(ph, c.idx)) {
+#pragma unroll
+    for (int q = 0; q < 2 * Q; ++q) {
+      pa[q * qs + c.idx] = Cd::enc((T)0);
+      pb[q * qs + c.idx] = Cd::enc((T)0);
+    }
+    return;
+  }
+  if (is_inflow(g, c.x, c.y, c.z)) {
+#pragma unroll
+    for (int q = 0; q < 2 * Q; ++q) pa[q * qs + c.idx] = in_eq[q];
+    return;
+  }
+  const double bx = beta0[c.idx], by = beta0[cells + c.idx], bz = beta0[2 * cells + c.idx];
+  const double g2 = 1.0 / (1.0 - (bx * bx + by * by + bz * bz));
+  const double e = e0[c.idx];
+  const double N = n0[c.idx] * sqrt(g2);
+  const EqCoef<T> k = eq_coef<T>(ph, N, e, (4.0 / 3.0) * e * g2, bx, by, bz);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    pa[q * qs + c.idx] = Cd::enc(feq_dev(k, q));
+    pa[(Q + q) * qs + c.idx] = Cd::enc(geq_dev(k, q));
+  }
+}
+
+// Inflow equilibrium (38 values in storage format), one thread.
+template <int ST>
+__global__ void k_inflow_eq(const Phys ph, double n, double e, double bx, double by, double bz,
+                            typename Codec<ST>::elem *__restrict__ out) {
+  using Cd = Codec<ST>;
+  using T = typename Cd::calc;
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double g2 = 1.0 / (1.0 - (bx * bx + by * by + bz * bz));
+  const EqCoef<T> k = eq_coef<T>(ph, n * sqrt(g2), e, (4.0 / 3.0) * e * g2, bx, by, bz);
+  for (int q = 0; q < Q; ++q) {
+    out[q] = Cd::enc(feq_dev(k, q));
+    out[Q + q] = Cd::enc(geq_dev(k, q));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fields and per-block conservation partials of a stored state.
+template <int ST>
+__global__ __launch_bounds__(BLOCK) void k_moments(const Geom g, const Phys ph,
+                                                   const typename Codec<ST>::elem *__restrict__ S,
+                                                   double *__restrict__ n, double *__restrict__ e,
+                                                   double *__restrict__ beta,
+                                                   double *__restrict__ part) {
+  using Cd = Codec<ST>;
+  const Cell c = decode_cell(g);
+  const size_t qs = (size_t)g.qs;
+  const size_t cells = (size_t)g.batch * g.per;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (c.active) {
+    if (solid_at(ph, c.idx)) {
+      if (n) n[c.idx] = 0.0;
+      if (e) e[c.idx] = 0.0;
+      if (beta) beta[c.idx] = beta[cells + c.idx] = beta[2 * cells + c.idx] = 0.0;
+    } else {
+      double N = 0.0, Eg = 0.0, sx, sy, sz, gv[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        N += (double)Cd::dec(S[q * qs + c.idx]);
+        gv[q] = (double)Cd::dec(S[(Q + q) * qs + c.idx]);
+        Eg += gv[q];
+      }
+      mirror_sums(gv, sx, sy, sz);
+      N += ph.n_ref;  // the rest parts sum to (n_ref, e_ref, 0)
+      Eg += ph.e_ref;
+      const Inv iv = invert(Eg, ph.c * sx, ph.c * sy, ph.c * sz);
+      if (n) n[c.idx] = N * sqrt(1.0 - (iv.bx * iv.bx + iv.by * iv.by + iv.bz * iv.bz));
+      if (e) e[c.idx] = iv.eps;
+      if (beta) {
+        beta[c.idx] = iv.bx;
+        beta[cells + c.idx] = iv.by;
+        beta[2 * cells + c.idx] = iv.bz;
+      }
+      acc[0] = N;
+      acc[1] = Eg;
+      acc[2] = iv.Mx;
+      acc[3] = iv.My;
+      acc[4] = iv.Mz;
+    }
+  }
+  if (part) {
+    double out[5];
+    block_sum<5>(acc, out);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 5; ++k) part[(size_t)c.L * 5 + k] = out[k];
+  }
+}
+
+// Per-instance, fixed-order reduction of [nblk][5] partials (one workgroup).
+//   res != null: res[b][k] = sum over the instance's blocks (k = 0..4);
+//   dtau != null: dtau[b] += sum of component 0;
+//   dinflow != null: dinflow[0..3] += sum over all blocks of components 1..4
+//   (order: e_in, beta_in x, y, z -> dL_de_in, dL_dbeta_in[3]).
+__global__ __launch_bounds__(BLOCK) void k_finish(const double *__restrict__ part, int batch,
+                                                  int nblk_per, double *__restrict__ res,
+                                                  double *__restrict__ dtau,
+                                                  double *__restrict__ de_in,
+                                                  double *__restrict__ dbeta_in) {
+  double total[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < batch; ++b) {
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int j = (int)threadIdx.x; j < nblk_per; j += BLOCK)
+      for (int k = 0; k < 5; ++k) v[k] += part[((size_t)b * nblk_per + j) * 5 + k];
+    double out[5];
+    block_sum<5>(v, out);
+    if (threadIdx.x == 0) {
+      if (res)
+        for (int k = 0; k < 5; ++k) res[b * 5 + k] = out[k];
+      if (dtau) dtau[b] += out[0];
+      for (int k = 0; k < 4; ++k) total[k] += out[1 + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (de_in) de_in[0] += total[0];
+    if (dbeta_in)
+      for (int k = 0; k < 3; ++k) dbeta_in[k] += total[1 + k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse mode.
+//
+// With g^eq_i = w_i [A_i e + W P_i(beta)] (A_i = 1/c_l^2, P_i = 3b_i +
+// (9/2) b_i^2 - s for i > 0; A_0 = -(2 + c_l^2)/c_l^2, P_0 = 3 - s) the
+// contraction of lambda with the equilibrium's partials is
+//   Le = sum l_i w_i A_i,  LW = sum l_i w_i P_i,
+//   Lb_a = (W / c_l) [sum_{i>0} l_i w_i e_ia (3 + 9 b_i) - 3 (beta_a / c_l) sum l_i w_i],
+// and the inversion's partials (D^2 = 4E^2 - 3|M|^2, e = D - E,
+// W = (2E + D)/3, beta = M/W) carry it to the moments:
+//   K = LW - Lb.beta / W,
+//   dL/dE = Le (4E/D - 1) + K (2 + 4E/D) / 3,
+//   dL/dM_a = -(M_a / D)(3 Le + K) + Lb_a / W.
+template <class T>
+struct LamSums {
+  T Slw, SW, Vx, Vy, Vz, lw0;
+};
+
+template <class T>
+__device__ __forceinline__ LamSums<T> lam_sums(const T (&lam)[Q], const EqCoef<T> &k) {
+  LamSums<T> r;
+  r.Slw = r.SW = (T)0;
+  T u[Q];
+  u[0] = (T)0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const T lw = lam[q] * (T)WQ[q];
+    r.Slw += lw;
+    if (q == 0) {
+      r.lw0 = lw;
+      r.SW += lw * ((T)3 - k.s);
+    } else {
+      const T b = dot_e(k, q);
+      r.SW += lw * (b * ((T)3 + (T)4.5 * b) - k.s);
+      u[q] = lw * ((T)3 + (T)9 * b);
+    }
+  }
+  mirror_sums(u, r.Vx, r.Vy, r.Vz);
+  return r;
+}
+
+struct LamEq {
+  double Le, LW, Lbx, Lby, Lbz;
+};
+
+template <class T>
+__device__ __forceinline__ LamEq lam_eq(const LamSums<T> &s, const Phys &ph, double W, double bx,
+                                        double by, double bz) {
+  LamEq r;
+  const double Slw = (double)s.Slw;
+  r.Le = Slw * ph.inv_c2 - (double)s.lw0 * (3.0 + ph.c * ph.c) * ph.inv_c2;
+  r.LW = (double)s.SW;
+  const double f = W * ph.inv_c;
+  r.Lbx = f * ((double)s.Vx - 3.0 * bx * ph.inv_c * Slw);
+  r.Lby = f * ((double)s.Vy - 3.0 * by * ph.inv_c * Slw);
+  r.Lbz = f * ((double)s.Vz - 3.0 * bz * ph.inv_c * Slw);
+  return r;
+}
+
+// (dL/dE, dL/dM) from contractions with respect to (e, W, beta).
+struct GradEM {
+  double gE, gx, gy, gz;
+};
+
+__device__ __forceinline__ GradEM chain_moments(const Inv &iv, double Le, double LW, double Lbx,
+                                                double Lby, double Lbz) {
+  GradEM r;
+  const double iW = 1.0 / iv.W, iD = 1.0 / iv.D;
+  const double K = LW - (Lbx * iv.bx + Lby * iv.by + Lbz * iv.bz) * iW;
+  const double rr = 4.0 * iv.E * iD;
+  r.gE = Le * (rr - 1.0) + K * (2.0 + rr) * (1.0 / 3.0);
+  const double h = (3.0 * Le + K) * iD;
+  r.gx = -iv.Mx * h + Lbx * iW;
+  r.gy = -iv.My * h + Lby * iW;
+  r.gz = -iv.Mz * h + Lbz * iW;
+  return r;
+}
+
+// d/d(e, beta) of w_i [A_i e + W P_i] at W = (4/3) e gamma^2, contracted with lambda.
+__device__ __forceinline__ void eq_param_grad(const LamEq &L, double e, double bx, double by,
+                                              double bz, double out[4]) {
+  const double g2 = 1.0 / (1.0 - (bx * bx + by * by + bz * bz));
+  const double W = (4.0 / 3.0) * e * g2;
+  out[0] = L.Le + (4.0 / 3.0) * g2 * L.LW;
+  const double t = 2.0 * W * g2 * L.LW;
+  out[1] = L.Lbx + t * bx;
+  out[2] = L.Lby + t * by;
+  out[3] = L.Lbz + t * bz;
+}
+
+// Does some update write lambda_t(x)_p in the main reverse kernel
+// (a streaming reader x + e_p, or x itself by bounce-back)?
+__device__ __forceinline__ bool covered(const Geom &g, const Phys &ph, const Cell &c, int p,
+                                        bool x_inflow) {
+  int r[3] = {c.x + EX[p], c.y + EY[p], c.z + EZ[p]};
+  bool inr = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int n = g.n[a];
+    if (g.periodic[a]) {
+      if (r[a] < 0) r[a] += n;
+      if (r[a] >= n) r[a] -= n;
+    } else if (r[a] < 0 || r[a] >= n) {
+      inr = false;
+    }
+  }
+  if (inr) {
+    const long long ri = cell_index(g, c.b, r[0], r[1], r[2]);
+    if (!solid_at(ph, ri) && !is_inflow(g, r[0], r[1], r[2])) return true;
+  }
+  if (!x_inflow) {
+    bool cl = false;
+    const int sx = resolve(g, 0, c.x + EX[p], cl);
+    const int sy = resolve(g, 1, c.y + EY[p], cl);
+    const int sz = resolve(g, 2, c.z + EZ[p], cl);
+    if (solid_at(ph, cell_index(g, c.b, sx, sy, sz))) return true;
+  }
+  return false;
+}
+
+// One reverse step of the g population (see rlb_adjoint_step).  Writes
+// lambda_t for every direction of every cell except the clamped-pull
+// contributions, which go to `scratch` (indexed by the reading cell) and are
+// added by k_adjoint_faces.  part[L][5] = (dtau, de_in, dbeta_in[3]) partials.
+template <int ST>
+__global__ __launch_bounds__(BLOCK) void k_adjoint(
+    const Geom g, const Phys ph, const typename Codec<ST>::elem *__restrict__ S,
+    const typename Codec<ST>::lam *__restrict__ lam_next,
+    typename Codec<ST>::lam *__restrict__ lam_out, typename Codec<ST>::lam *__restrict__ scratch,
+    double *__restrict__ part, const InflowState in) {
+  using Cd = Codec<ST>;
+  using T = typename Cd::calc;
+  using Lm = typename Cd::lam;
+  const Cell c = decode_cell(g);
+  const size_t qs = (size_t)g.qs;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (c.active) {
+    const uint8_t cls = ph.cls ? ph.cls[c.idx] : (uint8_t)0;
+    const bool solid = cls & CLS_SOLID;
+    const bool inflow = !solid && is_inflow(g, c.x, c.y, c.z);
+    const bool fast = !solid && !inflow && !(cls & CLS_NEAR) && in_fast(c, g.alo, g.ahi);
+    if (!fast) {
+      for (int p = 0; p < Q; ++p)
+        if (solid || !covered(g, ph, c, p, inflow)) lam_out[p * qs + c.idx] = (Lm)0;
+    }
+    if (inflow) {
+      T lam[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) lam[q] = (T)lam_next[q * qs + c.idx];
+      const double g2 = 1.0 / (1.0 - (in.bx * in.bx + in.by * in.by + in.bz * in.bz));
+      const double W = (4.0 / 3.0) * in.e * g2;
+      const EqCoef<T> k = eq_coef<T>(ph, 0.0, in.e, W, in.bx, in.by, in.bz);
+      const LamEq L = lam_eq(lam_sums(lam, k), ph, W, in.bx, in.by, in.bz);
+      double gr[4];
+      eq_param_grad(L, in.e, in.bx, in.by, in.bz, gr);
+      for (int k2 = 0; k2 < 4; ++k2) acc[1 + k2] = gr[k2];
+    } else if (!solid) {
+      T pre[Q], lam[Q];
+      if (fast) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) pre[q] = Cd::dec(S[q * qs + c.idx - g.off[q]]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const Pull p = pull_general(g, ph, c, q);
+          pre[q] = Cd::dec(S[p.q * qs + p.idx]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) lam[q] = (T)lam_next[q * qs + c.idx];
+      T sE = (T)0, sx, sy, sz;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) sE += pre[q];
+      mirror_sums(pre, sx, sy, sz);
+      const Inv iv = invert(ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
+                            ph.c * (double)sz);
+      const EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
+      const LamEq L = lam_eq(lam_sums(lam, k), ph, iv.W, iv.bx, iv.by, iv.bz);
+      const GradEM gm = chain_moments(iv, L.Le, L.LW, L.Lbx, L.Lby, L.Lbz);
+      const double om = ph.omega[c.b];
+      const T om1 = (T)(1.0 - om);
+      const T aE = (T)(om * gm.gE);
+      const T ax = (T)(om * ph.c * gm.gx), ay = (T)(om * ph.c * gm.gy),
+              az = (T)(om * ph.c * gm.gz);
+      T dt = (T)0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        dt += lam[q] * (pre[q] - geq_dev(k, q));
+        T mu = om1 * lam[q] + aE;
+        if (EX[q] == 1) mu += ax;
+        if (EX[q] == -1) mu -= ax;
+        if (EY[q] == 1) mu += ay;
+        if (EY[q] == -1) mu -= ay;
+        if (EZ[q] == 1) mu += az;
+        if (EZ[q] == -1) mu -= az;
+        if (fast) {
+          lam_out[q * qs + c.idx - g.off[q]] = (Lm)mu;
+        } else {
+          const Pull p = pull_general(g, ph, c, q);
+          if (p.bounce)
+            lam_out[OPP[q] * qs + c.idx] = (Lm)mu;
+          else if (p.clamped)
+            scratch[q * qs + c.idx] = (Lm)mu;
+          else
+            lam_out[q * qs + p.idx] = (Lm)mu;
+        }
+      }
+      acc[0] = om * om * (double)dt;
+    }
+  }
+  double out[5];
+  block_sum<5>(acc, out);
+  if (threadIdx.x == 0)
+    for (int k2 = 0; k2 < 5; ++k2) part[(size_t)c.L * 5 + k2] = out[k2];
+}
+
+// Faces of non-periodic axes, flattened: face f = (axis, side) holds
+// batch * (product of the other two extents) cells starting at start[f].
+struct Faces {
+  int count;
+  int axis[6], side[6];
+  long long start[7];
+};
+
+// Adds the contributions of clamped pulls (readers on an outflow face whose
+// source was clamped onto the same face) to lambda_t, in a fixed order.
+template <class Lm>
+__global__ __launch_bounds__(BLOCK) void k_adjoint_faces(const Geom g, const Phys ph, const Faces F,
+                                                         const Lm *__restrict__ scratch,
+                                                         Lm *__restrict__ lam_out) {
+  const long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (t >= F.start[F.count]) return;
+  int f = 0;
+  while (t >= F.start[f + 1]) ++f;
+  const int a = F.axis[f];
+  const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;  // the two other axes
+  long long r = t - F.start[f];
+  int co[3];
+  co[u] = (int)(r % g.n[u]);
+  r /= g.n[u];
+  co[v] = (int)(r % g.n[v]);
+  const int b = (int)(r / g.n[v]);
+  co[a] = F.side[f] == 0 ? 0 : g.n[a] - 1;
+  // a cell on several faces is handled by the first face listing it
+  for (int f2 = 0; f2 < f; ++f2) {
+    const int a2 = F.axis[f2];
+    if (co[a2] == (F.side[f2] == 0 ? 0 : g.n[a2] - 1)) return;
+  }
+  const long long yi = cell_index(g, b, co[0], co[1], co[2]);
+  if (solid_at(ph, yi)) return;
+  const size_t qs = (size_t)g.qs;
+  for (int p = 1; p < Q; ++p) {
+    const int e[3] = {EX[p], EY[p], EZ[p]};
+    int nrm[3];
+    bool hn[3], hc[3];
+    for (int k = 0; k < 3; ++k) {
+      const int n = g.n[k];
+      if (e[k] == 0) {
+        nrm[k] = co[k];
+        hn[k] = true;
+        hc[k] = false;
+        continue;
+      }
+      int rr = co[k] + e[k];
+      if (g.periodic[k]) {
+        if (rr < 0) rr += n;
+        if (rr >= n) rr -= n;
+        hn[k] = true;
+      } else {
+        hn[k] = rr >= 0 && rr < n;
+      }
+      nrm[k] = rr;
+      hc[k] = !g.periodic[k] && ((e[k] == 1 && co[k] == 0) || (e[k] == -1 && co[k] == n - 1));
+    }
+    Lm acc = (Lm)0;
+    bool any = false;
+    for (int m = 1; m < 8; ++m) {
+      int rc[3];
+      bool ok = true;
+      for (int k = 0; k < 3; ++k) {
+        if ((m >> k) & 1) {
+          ok = ok && hc[k];
+          rc[k] = co[k];
+        } else {
+          ok = ok && hn[k];
+          rc[k] = nrm[k];
+        }
+      }
+      if (!ok) continue;
+      const long long ri = cell_index(g, b, rc[0], rc[1], rc[2]);
+      if (solid_at(ph, ri) || is_inflow(g, rc[0], rc[1], rc[2])) continue;
+      acc += scratch[p * qs + ri];
+      any = true;
+    }
+    if (any) lam_out[p * qs + yi] += acc;
+  }
+}
+
+// lambda_T = (d(e, beta)/d S_T)^T (dL/de, dL/dbeta), cell-local.
+template <int ST>
+__global__ __launch_bounds__(BLOCK) void k_moments_adjoint(
+    const Geom g, const Phys ph, const typename Codec<ST>::elem *__restrict__ S,
+    const double *__restrict__ dLde, const double *__restrict__ dLdb,
+    typename Codec<ST>::lam *__restrict__ lam) {
+  using Cd = Codec<ST>;
+  using Lm = typename Cd::lam;
+  const Cell c = decode_cell(g);
+  if (!c.active) return;
+  const size_t qs = (size_t)g.qs;
+  const size_t cells = (size_t)g.batch * g.per;
+  if (solid_at(ph, c.idx)) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) lam[q * qs + c.idx] = (Lm)0;
+    return;
+  }
+  double sE = 0.0, sx, sy, sz, gv[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    gv[q] = (double)Cd::dec(S[q * qs + c.idx]);
+    sE += gv[q];
+  }
+  mirror_sums(gv, sx, sy, sz);
+  const Inv iv = invert(ph.e_ref + sE, ph.c * sx, ph.c * sy, ph.c * sz);
+  const GradEM gm = chain_moments(iv, dLde[c.idx], 0.0, dLdb[c.idx], dLdb[cells + c.idx],
+                                  dLdb[2 * cells + c.idx]);
+  const double ax = ph.c * gm.gx, ay = ph.c * gm.gy, az = ph.c * gm.gz;
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+    lam[q * qs + c.idx] = (Lm)(gm.gE + EX[q] * ax + EY[q] * ay + EZ[q] * az);
+}
+
+// lambda_0 -> dL/de0, dL/dbeta0 (overwritten) and inflow partials.
+template <int ST>
+__global__ __launch_bounds__(BLOCK) void k_init_adjoint(
+    const Geom g, const Phys ph, const double *__restrict__ e0, const double *__restrict__ beta0,
+    const typename Codec<ST>::lam *__restrict__ lam0, double *__restrict__ de0,
+    double *__restrict__ db0, double *__restrict__ part, const InflowState in) {
+  using Cd = Codec<ST>;
+  using T = typename Cd::calc;
+  const Cell c = decode_cell(g);
+  const size_t qs = (size_t)g.qs;
+  const size_t cells = (size_t)g.batch * g.per;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (c.active) {
+    de0[c.idx] = 0.0;
+    db0[c.idx] = db0[cells + c.idx] = db0[2 * cells + c.idx] = 0.0;
+    if (!solid_at(ph, c.idx)) {
+      const bool inflow = is_inflow(g, c.x, c.y, c.z);
+      T lam[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) lam[q] = (T)lam0[q * qs + c.idx];
+      const double e = inflow ? in.e : e0[c.idx];
+      const double bx = inflow ? in.bx : beta0[c.idx];
+      const double by = inflow ? in.by : beta0[cells + c.idx];
+      const double bz = inflow ? in.bz : beta0[2 * cells + c.idx];
+      const double g2 = 1.0 / (1.0 - (bx * bx + by * by + bz * bz));
+      const double W = (4.0 / 3.0) * e * g2;
+      const EqCoef<T> k = eq_coef<T>(ph, 0.0, e, W, bx, by, bz);
+      const LamEq L = lam_eq(lam_sums(lam, k), ph, W, bx, by, bz);
+      double gr[4];
+      eq_param_grad(L, e, bx, by, bz, gr);
+      if (inflow) {
+        for (int k2 = 0; k2 < 4; ++k2) acc[1 + k2] = gr[k2];
+      } else {
+        de0[c.idx] = gr[0];
+        db0[c.idx] = gr[1];
+        db0[cells + c.idx] = gr[2];
+        db0[2 * cells + c.idx] = gr[3];
+      }
+    }
+  }
+  double out[5];
+  block_sum<5>(acc, out);
+  if (threadIdx.x == 0)
+    for (int k2 = 0; k2 < 5; ++k2) part[(size_t)c.L * 5 + k2] = out[k2];
+}
+
+// Cell classes: solid bit from the caller's mask, "near" bit when any of the
+// 18 resolved neighbours is solid.
+__global__ __launch_bounds__(BLOCK) void k_classify(const Geom g, const uint8_t *__restrict__ solid,
+                                                    uint8_t *__restrict__ cls) {
+  const Cell c = decode_cell(g);
+  if (!c.active) return;
+  uint8_t v = solid[c.idx] ? CLS_SOLID : (uint8_t)0;
+  for (int q = 1; q < Q; ++q) {
+    bool cl = false;
+    const int sx = resolve(g, 0, c.x - EX[q], cl);
+    const int sy = resolve(g, 1, c.y - EY[q], cl);
+    const int sz = resolve(g, 2, c.z - EZ[q], cl);
+    if (solid[cell_index(g, c.b, sx, sy, sz)]) v |= CLS_NEAR;
+  }
+  cls[c.idx] = v;
+}
+
+}  // namespace rlb

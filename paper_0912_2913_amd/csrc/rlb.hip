@@ -1,0 +1,488 @@
+// Host side of librlb.so: parameter validation, launch geometry, storage
+// dispatch and the C entry points declared in include/rlb.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rlb.h"
+#include "kernels.hpp"
+
+using namespace rlb;
+
+struct rlb_solver {
+  rlb_params p;
+  Geom g;
+  Phys ph;
+  InflowState in;
+  Faces faces;
+  int st;
+  size_t elem, lam_elem;
+  void *pop[2];
+  int cur;
+  hipStream_t stream;
+  double *d_omega;
+  uint8_t *d_cls;
+  void *d_in_eq;
+  unsigned long long *d_counters;
+  double *d_part;
+  double *d_res;
+  void *d_scratch;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+rlb_status fail(rlb_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+#define RLB_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(RLB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+size_t elem_size(int st) {
+  switch (st) {
+    case ST_F64: return 8;
+    case ST_F32:
+    case ST_F32DEV: return 4;
+    case ST_F16DEV:
+    case ST_BF16DEV: return 2;
+  }
+  return 0;
+}
+
+FastDiv make_div(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  f.s = s;
+  f.m = (uint32_t)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+  return f;
+}
+
+long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
+
+rlb_status validate(const rlb_params *p, long long *cells_out) {
+  if (!p) return fail(RLB_EINVAL, "params is NULL");
+  const int n[3] = {p->nx, p->ny, p->nz};
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->batch < 1)
+    return fail(RLB_EINVAL, "extents and batch must be >= 1");
+  const long long cells = (long long)p->nx * p->ny * p->nz * p->batch;
+  if (cells > (1ll << 31) - 64) return fail(RLB_EINVAL, "too many cells (max 2^31 - 64)");
+  if (!(p->c_l > 0.0) || !std::isfinite(p->c_l)) return fail(RLB_EINVAL, "c_l must be > 0");
+  int inflow_faces = 0;
+  for (int a = 0; a < 3; ++a) {
+    for (int s = 0; s < 2; ++s) {
+      int b = p->bc[a][s];
+      if (b != RLB_BC_PERIODIC && b != RLB_BC_OUTFLOW && b != RLB_BC_INFLOW)
+        return fail(RLB_EINVAL, "unknown boundary code");
+      if (b == RLB_BC_INFLOW) ++inflow_faces;
+    }
+    if ((p->bc[a][0] == RLB_BC_PERIODIC) != (p->bc[a][1] == RLB_BC_PERIODIC))
+      return fail(RLB_EINVAL, "an axis is periodic on both faces or on neither");
+    if (p->bc[a][0] != RLB_BC_PERIODIC && n[a] < 2)
+      return fail(RLB_EINVAL, "a non-periodic axis needs at least 2 cells");
+  }
+  if (inflow_faces > 1) return fail(RLB_EINVAL, "at most one INFLOW face");
+  if (inflow_faces == 1) {
+    double b2 = p->inflow_beta[0] * p->inflow_beta[0] + p->inflow_beta[1] * p->inflow_beta[1] +
+                p->inflow_beta[2] * p->inflow_beta[2];
+    if (!(p->inflow_e > 0.0) || !std::isfinite(p->inflow_e))
+      return fail(RLB_EINVAL, "inflow_e must be > 0");
+    if (!(b2 < 1.0)) return fail(RLB_EINVAL, "|inflow_beta| must be < 1");
+    if (!std::isfinite(p->inflow_n)) return fail(RLB_EINVAL, "inflow_n must be finite");
+  }
+  if (elem_size(p->storage) == 0) return fail(RLB_EINVAL, "unknown storage");
+  if (p->storage >= ST_F32DEV) {
+    if (!(p->e_ref > 0.0) || !std::isfinite(p->e_ref) || !std::isfinite(p->n_ref))
+      return fail(RLB_EINVAL, "deviation storage needs e_ref > 0 and finite n_ref");
+  }
+  *cells_out = cells;
+  return RLB_OK;
+}
+
+void setup_geometry(rlb_solver *h) {
+  const rlb_params &p = h->p;
+  Geom &g = h->g;
+  std::memset(&g, 0, sizeof(g));
+  g.n[0] = p.nx;
+  g.n[1] = p.ny;
+  g.n[2] = p.nz;
+  g.batch = p.batch;
+  g.per = p.nx * p.ny * p.nz;
+  g.nblk_per = (g.per + BLOCK - 1) / BLOCK;
+  g.nblk = g.nblk_per * p.batch;
+  g.qs = round_up((long long)g.per * p.batch, 64);
+  g.div_x = make_div((uint32_t)p.nx);
+  g.div_y = make_div((uint32_t)p.ny);
+  g.div_blk = make_div((uint32_t)g.nblk_per);
+  const int stride[3] = {1, p.nx, p.nx * p.ny};
+  for (int a = 0; a < 3; ++a) {
+    g.periodic[a] = p.bc[a][0] == RLB_BC_PERIODIC;
+    g.inflow_lo[a] = p.bc[a][0] == RLB_BC_INFLOW;
+    g.inflow_hi[a] = p.bc[a][1] == RLB_BC_INFLOW;
+    if (g.inflow_lo[a] || g.inflow_hi[a]) g.any_inflow = 1;
+    if (g.periodic[a] && g.n[a] == 1) {
+      // every pull along this axis returns to the cell itself
+      g.flo[a] = g.fhi[a] = g.alo[a] = g.ahi[a] = 0;
+    } else {
+      g.flo[a] = 1;
+      g.fhi[a] = g.n[a] - 2;
+      g.alo[a] = 1 + (g.inflow_lo[a] ? 1 : 0);
+      g.ahi[a] = g.n[a] - 2 - (g.inflow_hi[a] ? 1 : 0);
+    }
+  }
+  const int e[Q][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                       {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                       {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                       {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  for (int q = 0; q < Q; ++q) {
+    int o = 0;
+    for (int a = 0; a < 3; ++a)
+      if (!(g.periodic[a] && g.n[a] == 1)) o += e[q][a] * stride[a];
+    g.off[q] = o;
+  }
+  Faces &F = h->faces;
+  std::memset(&F, 0, sizeof(F));
+  long long acc = 0;
+  for (int a = 0; a < 3; ++a) {
+    if (g.periodic[a]) continue;
+    const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
+    for (int s = 0; s < 2; ++s) {
+      F.axis[F.count] = a;
+      F.side[F.count] = s;
+      F.start[F.count] = acc;
+      acc += (long long)p.batch * g.n[u] * g.n[v];
+      ++F.count;
+    }
+  }
+  F.start[F.count] = acc;
+}
+
+unsigned grid_blocks(const rlb_solver *h) { return (unsigned)h->g.nblk; }
+
+template <int ST>
+rlb_status launch_init(rlb_solver *h, const double *n0, const double *e0, const double *beta0) {
+  using El = typename Codec<ST>::elem;
+  const rlb_params &p = h->p;
+  hipLaunchKernelGGL(k_inflow_eq<ST>, dim3(1), dim3(64), 0, h->stream, h->ph, p.inflow_n,
+                     p.inflow_e, p.inflow_beta[0], p.inflow_beta[1], p.inflow_beta[2],
+                     (El *)h->d_in_eq);
+  hipLaunchKernelGGL(k_init<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
+                     n0, e0, beta0, (El *)h->pop[0], (El *)h->pop[1], (const El *)h->d_in_eq);
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
+}
+
+template <int ST>
+rlb_status launch_steps(rlb_solver *h, int nsteps) {
+  using El = typename Codec<ST>::elem;
+  for (int s = 0; s < nsteps; ++s) {
+    hipLaunchKernelGGL((k_step<ST, true>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+                       h->ph, (const El *)h->pop[h->cur], (El *)h->pop[1 - h->cur],
+                       (const El *)h->d_in_eq, h->d_counters);
+    h->cur = 1 - h->cur;
+  }
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
+}
+
+template <int ST>
+rlb_status launch_step_g(rlb_solver *h, const void *src, void *dst) {
+  using El = typename Codec<ST>::elem;
+  hipLaunchKernelGGL((k_step<ST, false>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+                     h->ph, (const El *)src, (El *)dst, (const El *)h->d_in_eq, h->d_counters);
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
+}
+
+template <int ST>
+rlb_status launch_moments(rlb_solver *h, double *n, double *e, double *beta, bool sums) {
+  using El = typename Codec<ST>::elem;
+  hipLaunchKernelGGL(k_moments<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
+                     (const El *)h->pop[h->cur], n, e, beta, sums ? h->d_part : nullptr);
+  if (sums)
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(BLOCK), 0, h->stream, h->d_part, h->p.batch,
+                       h->g.nblk_per, h->d_res, nullptr, nullptr, nullptr);
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
+}
+
+template <int ST>
+rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_next, void *lam_out,
+                          double *dtau, double *dbeta_in, double *de_in) {
+  using El = typename Codec<ST>::elem;
+  using Lm = typename Codec<ST>::lam;
+  hipLaunchKernelGGL(k_adjoint<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
+                     (const El *)S, (const Lm *)lam_next, (Lm *)lam_out, (Lm *)h->d_scratch,
+                     h->d_part, h->in);
+  if (h->faces.count > 0) {
+    const long long nf = h->faces.start[h->faces.count];
+    hipLaunchKernelGGL(k_adjoint_faces<Lm>, dim3((unsigned)((nf + BLOCK - 1) / BLOCK)),
+                       dim3(BLOCK), 0, h->stream, h->g, h->ph, h->faces,
+                       (const Lm *)h->d_scratch, (Lm *)lam_out);
+  }
+  if (dtau || dbeta_in || de_in)
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(BLOCK), 0, h->stream, h->d_part, h->p.batch,
+                       h->g.nblk_per, nullptr, dtau, de_in, dbeta_in);
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
+}
+
+template <int ST>
+rlb_status launch_moments_adjoint(rlb_solver *h, const void *S, const double *dLde,
+                                  const double *dLdb, void *lam) {
+  using El = typename Codec<ST>::elem;
+  using Lm = typename Codec<ST>::lam;
+  hipLaunchKernelGGL(k_moments_adjoint<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream,
+                     h->g, h->ph, (const El *)S, dLde, dLdb, (Lm *)lam);
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
+}
+
+template <int ST>
+rlb_status launch_init_adjoint(rlb_solver *h, const double *e0, const double *beta0,
+                               const void *lam0, double *de0, double *db0, double *dbeta_in,
+                               double *de_in) {
+  using Lm = typename Codec<ST>::lam;
+  hipLaunchKernelGGL(k_init_adjoint<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+                     h->ph, e0, beta0, (const Lm *)lam0, de0, db0, h->d_part, h->in);
+  if (dbeta_in || de_in)
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(BLOCK), 0, h->stream, h->d_part, h->p.batch,
+                       h->g.nblk_per, nullptr, nullptr, de_in, dbeta_in);
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
+}
+
+// Storage dispatch: DISPATCH(fn, args...) calls fn<ST>(args...).
+#define RLB_DISPATCH(st, fn, ...)                                       \
+  switch (st) {                                                         \
+    case ST_F64: return fn<ST_F64>(__VA_ARGS__);                        \
+    case ST_F32: return fn<ST_F32>(__VA_ARGS__);                        \
+    case ST_F32DEV: return fn<ST_F32DEV>(__VA_ARGS__);                  \
+    case ST_F16DEV: return fn<ST_F16DEV>(__VA_ARGS__);                  \
+    case ST_BF16DEV: return fn<ST_BF16DEV>(__VA_ARGS__);                \
+  }                                                                     \
+  return fail(RLB_EINVAL, "unknown storage")
+
+void free_solver(rlb_solver *h) {
+  if (!h) return;
+  if (h->d_omega) (void)hipFree(h->d_omega);
+  if (h->d_cls) (void)hipFree(h->d_cls);
+  if (h->d_in_eq) (void)hipFree(h->d_in_eq);
+  if (h->d_counters) (void)hipFree(h->d_counters);
+  if (h->d_part) (void)hipFree(h->d_part);
+  if (h->d_res) (void)hipFree(h->d_res);
+  if (h->d_scratch) (void)hipFree(h->d_scratch);
+  delete h;
+}
+
+rlb_status check_handle(const rlb_solver *h) {
+  if (!h) return fail(RLB_EINVAL, "solver handle is NULL");
+  return RLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rlb_status rlb_buffer_layout(const rlb_params *p, int64_t *q_stride, int64_t *state_bytes) {
+  long long cells = 0;
+  rlb_status s = validate(p, &cells);
+  if (s != RLB_OK) return s;
+  const long long qs = round_up(cells, 64);
+  if (q_stride) *q_stride = qs;
+  if (state_bytes) *state_bytes = 2LL * Q * qs * (long long)elem_size(p->storage);
+  return RLB_OK;
+}
+
+rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
+                    const uint8_t *solid, const double *n0, const double *e0,
+                    const double *beta0, void *pop_a, void *pop_b, void *stream) {
+  g_err.clear();
+  if (!out) return fail(RLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  long long cells = 0;
+  rlb_status s = validate(p, &cells);
+  if (s != RLB_OK) return s;
+  if (!tau || !n0 || !e0 || !beta0 || !pop_a || !pop_b)
+    return fail(RLB_EINVAL, "a required pointer is NULL");
+  if (pop_a == pop_b) return fail(RLB_EINVAL, "pop_a and pop_b must differ");
+  for (int b = 0; b < p->batch; ++b)
+    if (!(tau[b] > 0.5) || !std::isfinite(tau[b]))
+      return fail(RLB_EINVAL, "tau must be > 1/2 (positive viscosity) for every instance");
+
+  rlb_solver *h = new rlb_solver;
+  std::memset(h, 0, sizeof(*h));
+  h->p = *p;
+  h->st = p->storage;
+  h->elem = elem_size(p->storage);
+  h->lam_elem = p->storage == RLB_F64 ? 8 : 4;
+  h->pop[0] = pop_a;
+  h->pop[1] = pop_b;
+  h->cur = 0;
+  h->stream = (hipStream_t)stream;
+  setup_geometry(h);
+
+  Phys &ph = h->ph;
+  ph.c = p->c_l;
+  ph.inv_c = 1.0 / p->c_l;
+  ph.inv_c2 = 1.0 / (p->c_l * p->c_l);
+  ph.k0 = 3.0 - 2.0 / (p->c_l * p->c_l);
+  const bool dev = p->storage >= ST_F32DEV;
+  ph.n_ref = dev ? p->n_ref : 0.0;
+  ph.e_ref = dev ? p->e_ref : 0.0;
+  h->in.e = p->inflow_e;
+  h->in.bx = p->inflow_beta[0];
+  h->in.by = p->inflow_beta[1];
+  h->in.bz = p->inflow_beta[2];
+
+  auto cleanup_fail = [&](hipError_t e, const char *what) {
+    free_solver(h);
+    return fail(RLB_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  hipError_t e;
+  std::vector<double> om(p->batch);
+  for (int b = 0; b < p->batch; ++b) om[b] = 1.0 / tau[b];
+  if ((e = hipMalloc(&h->d_omega, sizeof(double) * p->batch)) != hipSuccess)
+    return cleanup_fail(e, "hipMalloc(omega)");
+  if ((e = hipMemcpyAsync(h->d_omega, om.data(), sizeof(double) * p->batch,
+                          hipMemcpyHostToDevice, h->stream)) != hipSuccess)
+    return cleanup_fail(e, "copy omega");
+  if ((e = hipMalloc(&h->d_in_eq, 2 * Q * 8)) != hipSuccess)
+    return cleanup_fail(e, "hipMalloc(inflow)");
+  if ((e = hipMalloc(&h->d_counters, 2 * sizeof(unsigned long long))) != hipSuccess)
+    return cleanup_fail(e, "hipMalloc(counters)");
+  if ((e = hipMemsetAsync(h->d_counters, 0, 2 * sizeof(unsigned long long), h->stream)) !=
+      hipSuccess)
+    return cleanup_fail(e, "clear counters");
+  if ((e = hipMalloc(&h->d_part, sizeof(double) * 5 * (size_t)h->g.nblk)) != hipSuccess)
+    return cleanup_fail(e, "hipMalloc(partials)");
+  if ((e = hipMalloc(&h->d_res, sizeof(double) * 5 * (size_t)p->batch)) != hipSuccess)
+    return cleanup_fail(e, "hipMalloc(results)");
+  if (solid) {
+    if ((e = hipMalloc(&h->d_cls, (size_t)h->g.qs)) != hipSuccess)
+      return cleanup_fail(e, "hipMalloc(classes)");
+    hipLaunchKernelGGL(k_classify, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, solid,
+                       h->d_cls);
+    ph.cls = h->d_cls;
+  }
+  ph.omega = h->d_omega;
+  auto launch = [&]() -> rlb_status { RLB_DISPATCH(h->st, launch_init, h, n0, e0, beta0); };
+  s = launch();
+  if (s == RLB_OK && (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+    s = fail(RLB_EDEVICE, std::string("rlb_init: ") + hipGetErrorString(e));
+  if (s != RLB_OK) {
+    free_solver(h);
+    return s;
+  }
+  *out = h;
+  return RLB_OK;
+}
+
+rlb_status rlb_step(rlb_solver *h, int32_t nsteps) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (nsteps < 0) return fail(RLB_EINVAL, "nsteps must be >= 0");
+  RLB_DISPATCH(h->st, launch_steps, h, nsteps);
+}
+
+rlb_status rlb_step_g(rlb_solver *h, const void *g_src, void *g_dst) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (!g_src || !g_dst || g_src == g_dst) return fail(RLB_EINVAL, "g_src/g_dst invalid");
+  RLB_DISPATCH(h->st, launch_step_g, h, g_src, g_dst);
+}
+
+rlb_status rlb_current(rlb_solver *h, void **state) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (!state) return fail(RLB_EINVAL, "state is NULL");
+  *state = h->pop[h->cur];
+  return RLB_OK;
+}
+
+rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double *sums) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  auto launch = [&]() -> rlb_status {
+    RLB_DISPATCH(h->st, launch_moments, h, n, e, beta, sums != nullptr);
+  };
+  rlb_status s = launch();
+  if (s != RLB_OK || !sums) return s;
+  RLB_HIP(hipMemcpyAsync(sums, h->d_res, sizeof(double) * 5 * h->p.batch, hipMemcpyDeviceToHost,
+                         h->stream));
+  RLB_HIP(hipStreamSynchronize(h->stream));
+  return RLB_OK;
+}
+
+rlb_status rlb_counters(rlb_solver *h, int64_t counts[2]) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (!counts) return fail(RLB_EINVAL, "counts is NULL");
+  unsigned long long c[2];
+  RLB_HIP(hipMemcpyAsync(c, h->d_counters, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+  RLB_HIP(hipStreamSynchronize(h->stream));
+  RLB_HIP(hipMemsetAsync(h->d_counters, 0, sizeof(c), h->stream));
+  counts[0] = (int64_t)c[0];
+  counts[1] = (int64_t)c[1];
+  return c[0] > 0 ? RLB_EUNPHYSICAL : RLB_OK;
+}
+
+rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *lam_next,
+                            void *lam_out, double *dL_dtau, double *dL_dbeta_in,
+                            double *dL_de_in) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (!g_state_t || !lam_next || !lam_out || lam_next == lam_out)
+    return fail(RLB_EINVAL, "adjoint buffers invalid");
+  if (h->faces.count > 0 && !h->d_scratch)
+    RLB_HIP(hipMalloc(&h->d_scratch, (size_t)Q * h->g.qs * h->lam_elem));
+  RLB_DISPATCH(h->st, launch_adjoint, h, g_state_t, lam_next, lam_out, dL_dtau, dL_dbeta_in,
+               dL_de_in);
+}
+
+rlb_status rlb_moments_adjoint(rlb_solver *h, const void *g_state_T, const double *dL_de,
+                               const double *dL_dbeta, void *lam_T) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (!g_state_T || !dL_de || !dL_dbeta || !lam_T)
+    return fail(RLB_EINVAL, "a required pointer is NULL");
+  RLB_DISPATCH(h->st, launch_moments_adjoint, h, g_state_T, dL_de, dL_dbeta, lam_T);
+}
+
+rlb_status rlb_init_adjoint(rlb_solver *h, const double *e0, const double *beta0,
+                            const void *lam_0, double *dL_de0, double *dL_dbeta0,
+                            double *dL_dbeta_in, double *dL_de_in) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (!e0 || !beta0 || !lam_0 || !dL_de0 || !dL_dbeta0)
+    return fail(RLB_EINVAL, "a required pointer is NULL");
+  RLB_DISPATCH(h->st, launch_init_adjoint, h, e0, beta0, lam_0, dL_de0, dL_dbeta0, dL_dbeta_in,
+               dL_de_in);
+}
+
+rlb_status rlb_destroy(rlb_solver *h) {
+  if (!h) return RLB_OK;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  free_solver(h);
+  if (e != hipSuccess) return fail(RLB_EDEVICE, hipGetErrorString(e));
+  return RLB_OK;
+}
+
+const char *rlb_status_string(rlb_status s) {
+  switch (s) {
+    case RLB_OK: return "ok";
+    case RLB_EINVAL: return "invalid argument";
+    case RLB_ENOMEM: return "out of memory";
+    case RLB_EDEVICE: return "device error";
+    case RLB_EUNPHYSICAL: return "unphysical state (no real inversion of the moments)";
+  }
+  return "unknown status";
+}
+
+const char *rlb_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,170 @@
+"""Python face of librlb.so: device buffers and streams from PyTorch, all
+arithmetic in the library's HIP kernels (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+STORAGE_DTYPE = {
+    _lib.F64: torch.float64,
+    _lib.F32: torch.float32,
+    _lib.F32DEV: torch.float32,
+    _lib.F16DEV: torch.float16,
+    _lib.BF16DEV: torch.bfloat16,
+}
+Q = 19
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def make_params(nx, ny, nz, batch=1, c_l=1.0, bc=((0, 0), (0, 0), (0, 0)),
+                inflow=(1.0, 1.0, 0.0, 0.0, 0.0), storage=_lib.F64, n_ref=1.0,
+                e_ref=1.0) -> _lib.Params:
+    p = _lib.Params()
+    p.nx, p.ny, p.nz, p.batch = int(nx), int(ny), int(nz), int(batch)
+    p.c_l = float(c_l)
+    for a in range(3):
+        for s in range(2):
+            p.bc[a][s] = int(bc[a][s])
+    p.inflow_n, p.inflow_e = float(inflow[0]), float(inflow[1])
+    for k in range(3):
+        p.inflow_beta[k] = float(inflow[2 + k])
+    p.storage = int(storage)
+    p.n_ref, p.e_ref = float(n_ref), float(e_ref)
+    return p
+
+
+def buffer_layout(p: _lib.Params) -> Tuple[int, int]:
+    qs = ctypes.c_int64()
+    nb = ctypes.c_int64()
+    check(_lib.lib().rlb_buffer_layout(ctypes.byref(p), ctypes.byref(qs), ctypes.byref(nb)),
+          "rlb_buffer_layout")
+    return qs.value, nb.value
+
+
+class Solver:
+    """One RLB lattice problem resident on a GPU.
+
+    ``setup`` is any object with the attributes of ``rlb_inputs.Setup`` (extents,
+    batch, c_l, bc, inflow, tau, storage, n_ref, e_ref, n0, e0, beta0, solid).
+    """
+
+    def __init__(self, setup, device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None):
+        _lib.lib()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        s = setup
+        self.setup = s
+        self.params = make_params(s.nx, s.ny, s.nz, s.batch, s.c_l, s.bc, s.inflow, s.storage,
+                                  s.n_ref, s.e_ref)
+        self.nx, self.ny, self.nz, self.batch = s.nx, s.ny, s.nz, s.batch
+        self.cells = s.batch * s.nz * s.ny * s.nx
+        self.storage = int(s.storage)
+        self.dtype = STORAGE_DTYPE[self.storage]
+        self.lam_dtype = torch.float64 if self.storage == _lib.F64 else torch.float32
+        self.q_stride, self.state_bytes = buffer_layout(self.params)
+        with torch.cuda.stream(self.stream):
+            self.pop = [torch.empty((2, Q, self.q_stride), dtype=self.dtype, device=self.device)
+                        for _ in range(2)]
+            f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(self.device)
+            n0 = f64(np.asarray(s.n0).reshape(-1))
+            e0 = f64(np.asarray(s.e0).reshape(-1))
+            b0 = f64(np.asarray(s.beta0).reshape(3, -1))
+            self.e0_dev, self.beta0_dev = e0, b0
+            self.solid = None
+            if s.solid is not None:
+                self.solid = torch.as_tensor(np.ascontiguousarray(s.solid.reshape(-1), np.uint8)).to(self.device)
+        self.tau = np.ascontiguousarray(np.asarray(s.tau, dtype=np.float64).reshape(-1))
+        if self.tau.size == 1 and self.batch > 1:
+            self.tau = np.full(self.batch, self.tau[0])
+        h = ctypes.c_void_p()
+        check(_lib.lib().rlb_init(ctypes.byref(h), ctypes.byref(self.params),
+                                  self.tau.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  _ptr(self.solid), _ptr(n0), _ptr(e0), _ptr(b0),
+                                  _ptr(self.pop[0]), _ptr(self.pop[1]),
+                                  ctypes.c_void_p(self.stream.cuda_stream)), "rlb_init")
+        self.h = h
+
+    # ------------------------------------------------------------------ forward
+    def step(self, nsteps: int = 1):
+        check(_lib.lib().rlb_step(self.h, int(nsteps)), "rlb_step")
+
+    def step_g(self, g_src: torch.Tensor, g_dst: torch.Tensor):
+        check(_lib.lib().rlb_step_g(self.h, _ptr(g_src), _ptr(g_dst)), "rlb_step_g")
+
+    def state(self) -> torch.Tensor:
+        """The buffer holding the current state, [2][19][q_stride] (a view, not a copy)."""
+        p = ctypes.c_void_p()
+        check(_lib.lib().rlb_current(self.h, ctypes.byref(p)), "rlb_current")
+        for t in self.pop:
+            if t.data_ptr() == p.value:
+                return t
+        raise RuntimeError("current state is not one of the solver's buffers")
+
+    def g_state(self) -> torch.Tensor:
+        return self.state()[1]
+
+    def new_g(self) -> torch.Tensor:
+        return torch.empty((Q, self.q_stride), dtype=self.dtype, device=self.device)
+
+    def new_lam(self) -> torch.Tensor:
+        return torch.empty((Q, self.q_stride), dtype=self.lam_dtype, device=self.device)
+
+    def moments(self, sums: bool = False):
+        """(n, e, beta[3]) device float64 tensors of shape [cells] / [3, cells];
+        with sums=True also the host [batch][5] conservation sums."""
+        n = torch.empty(self.cells, dtype=torch.float64, device=self.device)
+        e = torch.empty_like(n)
+        b = torch.empty((3, self.cells), dtype=torch.float64, device=self.device)
+        out = None
+        sp = None
+        if sums:
+            out = np.zeros((self.batch, 5))
+            sp = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        check(_lib.lib().rlb_moments(self.h, _ptr(n), _ptr(e), _ptr(b), sp), "rlb_moments")
+        return (n, e, b, out) if sums else (n, e, b)
+
+    def counters(self, raise_on_unphysical: bool = False):
+        c = (ctypes.c_int64 * 2)()
+        st = _lib.lib().rlb_counters(self.h, c)
+        if st == _lib.RLB_EUNPHYSICAL and not raise_on_unphysical:
+            return int(c[0]), int(c[1])
+        check(st, "rlb_counters")
+        return int(c[0]), int(c[1])
+
+    # ------------------------------------------------------------------ reverse
+    def adjoint_step(self, g_state_t, lam_next, lam_out, dtau=None, dbeta_in=None, de_in=None):
+        check(_lib.lib().rlb_adjoint_step(self.h, _ptr(g_state_t), _ptr(lam_next), _ptr(lam_out),
+                                          _ptr(dtau), _ptr(dbeta_in), _ptr(de_in)),
+              "rlb_adjoint_step")
+
+    def moments_adjoint(self, g_state_T, dLde, dLdb, lam_T):
+        check(_lib.lib().rlb_moments_adjoint(self.h, _ptr(g_state_T), _ptr(dLde), _ptr(dLdb),
+                                             _ptr(lam_T)), "rlb_moments_adjoint")
+
+    def init_adjoint(self, lam0, de0, db0, dbeta_in=None, de_in=None, e0=None, beta0=None):
+        e0 = self.e0_dev if e0 is None else e0
+        beta0 = self.beta0_dev if beta0 is None else beta0
+        check(_lib.lib().rlb_init_adjoint(self.h, _ptr(e0), _ptr(beta0), _ptr(lam0), _ptr(de0),
+                                          _ptr(db0), _ptr(dbeta_in), _ptr(de_in)),
+              "rlb_init_adjoint")
+
+    # ------------------------------------------------------------------ misc
+    def close(self):
+        if getattr(self, "h", None):
+            check(_lib.lib().rlb_destroy(self.h), "rlb_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,118 @@
+"""The C ABI library: it loads, exports every function include/rlb.h declares, and
+rejects invalid problem statements before touching the device (CPU-only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rlb.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_0912_2913_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rlb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_core_entry_points():
+    names = declared_functions()
+    for core in ("rlb_init", "rlb_step", "rlb_moments", "rlb_adjoint_step"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    lib = L.lib()
+    names = declared_functions()
+    assert sorted(L.EXPORTS) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(L):
+    assert L.status_string(L.RLB_OK) == "ok"
+    assert "invalid" in L.status_string(L.RLB_EINVAL)
+    assert "unphysical" in L.status_string(L.RLB_EUNPHYSICAL)
+
+
+def _params(L, **kw):
+    from paper_0912_2913_amd.solver import make_params
+
+    base = dict(nx=8, ny=8, nz=8)
+    base.update(kw)
+    return make_params(**base)
+
+
+def test_buffer_layout_pads_direction_stride(L):
+    from paper_0912_2913_amd.solver import buffer_layout
+
+    qs, nb = buffer_layout(_params(L, nx=1, ny=1, nz=800))
+    assert qs == 832 and nb == 2 * 19 * 832 * 8
+    qs, nb = buffer_layout(_params(L, nx=256, ny=256, nz=256, storage=L.BF16DEV))
+    assert qs == 256 ** 3 and nb == 2 * 19 * 256 ** 3 * 2
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0),
+    dict(batch=0),
+    dict(c_l=0.0),
+    dict(c_l=float("nan")),
+    dict(bc=((0, 1), (0, 0), (0, 0))),           # periodic on one face only
+    dict(bc=((7, 7), (0, 0), (0, 0))),           # unknown code
+    dict(bc=((2, 2), (0, 0), (0, 0))),           # two inflow faces
+    dict(bc=((2, 1), (0, 0), (0, 0)), inflow=(1.0, 1.0, 1.0, 0.0, 0.0)),   # |beta_in| = 1
+    dict(bc=((2, 1), (0, 0), (0, 0)), inflow=(1.0, -1.0, 0.1, 0.0, 0.0)),  # e_in <= 0
+    dict(nx=1, bc=((1, 1), (0, 0), (0, 0))),     # non-periodic axis of one cell
+    dict(storage=9),
+    dict(storage=4, e_ref=0.0),
+    dict(nx=2048, ny=2048, nz=1024),             # > 2^31 cells
+])
+def test_invalid_problem_statement_is_rejected(L, bad):
+    from paper_0912_2913_amd.solver import make_params
+
+    p = make_params(**{**dict(nx=8, ny=8, nz=8), **bad})
+    st = L.lib().rlb_buffer_layout(ctypes.byref(p), None, None)
+    assert st == L.RLB_EINVAL
+    assert L.lib().rlb_last_error().decode() != ""
+
+
+def test_init_rejects_bad_tau_and_null_buffers_without_device_work(L):
+    p = _params(L)
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    for tau in (0.5, 0.3, float("nan")):
+        t = np.array([tau])
+        st = L.lib().rlb_init(ctypes.byref(h), ctypes.byref(p),
+                              t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, fake, fake,
+                              fake, fake, ctypes.c_void_p(0x2000), None)
+        assert st == L.RLB_EINVAL
+    t = np.array([0.7])
+    st = L.lib().rlb_init(ctypes.byref(h), ctypes.byref(p),
+                          t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None, fake,
+                          fake, fake, fake, None)
+    assert st == L.RLB_EINVAL
+    st = L.lib().rlb_init(ctypes.byref(h), ctypes.byref(p),
+                          t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, fake, fake,
+                          fake, fake, fake, None)  # pop_a == pop_b
+    assert st == L.RLB_EINVAL
+
+
+def test_null_handle_is_rejected(L):
+    lib = L.lib()
+    assert lib.rlb_step(None, 1) == L.RLB_EINVAL
+    assert lib.rlb_moments(None, None, None, None, None) == L.RLB_EINVAL
+    assert lib.rlb_adjoint_step(None, None, None, None, None, None, None) == L.RLB_EINVAL
+    assert lib.rlb_destroy(None) == L.RLB_OK
