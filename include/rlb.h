@@ -125,6 +125,11 @@ rlb_status rlb_current(rlb_solver *h, void **state);
  * sums != NULL the call synchronises the stream. */
 rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double *sums);
 
+/* Fields e [cells] and beta [3][cells] (device double, either may be NULL)
+ * of a g block (any state of the g population, e.g. one from rlb_step_g):
+ * the constraints for (e, beta) involve g alone.  Zeros on solid cells. */
+rlb_status rlb_fields_g(rlb_solver *h, const void *g_state, double *e, double *beta);
+
 /* Counters of the steps run since the last call (synchronises): counts[0] =
  * unphysical g updates (4E^2 - 3|M|^2 <= 0, e <= 0, |beta| >= 1 or NaN);
  * counts[1] = f updates whose equilibrium had a non-positive component

@@ -19,7 +19,7 @@ F64, F32, F32DEV, F16DEV, BF16DEV = 0, 1, 2, 3, 4
 # Every symbol include/rlb.h declares (checked by the tests).
 EXPORTS = (
     "rlb_buffer_layout", "rlb_init", "rlb_step", "rlb_step_g", "rlb_current", "rlb_moments",
-    "rlb_counters", "rlb_adjoint_step", "rlb_moments_adjoint", "rlb_init_adjoint",
+    "rlb_fields_g", "rlb_counters", "rlb_adjoint_step", "rlb_moments_adjoint", "rlb_init_adjoint",
     "rlb_destroy", "rlb_status_string", "rlb_last_error",
 )
 
@@ -68,6 +68,7 @@ def lib():
     L.rlb_step_g.argtypes = [vp, vp, vp]
     L.rlb_current.argtypes = [vp, ctypes.POINTER(vp)]
     L.rlb_moments.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
+    L.rlb_fields_g.argtypes = [vp, vp, vp, vp]
     L.rlb_counters.argtypes = [vp, i64p]
     L.rlb_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.rlb_moments_adjoint.argtypes = [vp, vp, vp, vp, vp]
@@ -78,7 +79,7 @@ def lib():
     L.rlb_last_error.argtypes = []
     L.rlb_last_error.restype = ctypes.c_char_p
     for name in ("rlb_buffer_layout", "rlb_init", "rlb_step", "rlb_step_g", "rlb_current",
-                 "rlb_moments", "rlb_counters", "rlb_adjoint_step", "rlb_moments_adjoint",
+                 "rlb_moments", "rlb_fields_g", "rlb_counters", "rlb_adjoint_step", "rlb_moments_adjoint",
                  "rlb_init_adjoint", "rlb_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L

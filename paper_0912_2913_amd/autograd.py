@@ -1,0 +1,168 @@
+"""Differentiable RLB runs: a torch.autograd.Function over the library's forward
+and adjoint kernels, with sqrt(T) checkpointing of the g population.
+
+Only the energy-momentum population g enters (e, beta) (the constraint for n
+involves f alone and f^eq depends on beta only), so a loss on the final (e, beta)
+fields has zero derivative with respect to f and the reverse sweep runs on g
+alone: every checkpoint and recomputed state is a g block in the solver's
+storage format, and the recompute is bit-identical to the forward.
+
+Schedule for T steps with segment length S (default ceil(sqrt(T))):
+  forward  -- g-only steps from S_0; keep S_0, S_S, S_2S, ... (K = ceil(T/S));
+  backward -- lambda_T from the moment map; for each segment from the last:
+              restore its checkpoint, recompute and keep its S states, then run
+              the adjoint steps down through the segment; finally map lambda_0 to
+              the initial fields.
+Peak storage: K checkpoints + S segment states + 2 lambda buffers.  S = T keeps
+every state (store-all).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import replace
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from .solver import Solver
+
+
+def segment_length(T: int, mode="sqrt") -> int:
+    if T <= 0:
+        return 1
+    if mode == "store_all":
+        return T
+    if isinstance(mode, int):
+        return max(1, min(T, mode))
+    return max(1, int(math.ceil(math.sqrt(T))))
+
+
+class GRun:
+    """A g-only forward run of T steps on one solver with checkpoints."""
+
+    def __init__(self, solver: Solver, T: int, seg: int):
+        self.sv = solver
+        self.T = int(T)
+        self.S = int(seg)
+        self.K = (self.T + self.S - 1) // self.S if self.T > 0 else 1
+        self.ckpt: List[torch.Tensor] = []
+        self.final: Optional[torch.Tensor] = None
+
+    def forward(self):
+        sv = self.sv
+        a = sv.g_state().clone()  # S_0
+        b = sv.new_g()
+        self.ckpt = []
+        for t in range(self.T):
+            if t % self.S == 0:
+                self.ckpt.append(a.clone())
+            sv.step_g(a, b)
+            a, b = b, a
+        if self.T == 0:
+            self.ckpt.append(a.clone())
+        self.final = a
+        return sv.fields_g(a)
+
+    def backward(self, dLde: torch.Tensor, dLdb: torch.Tensor):
+        sv = self.sv
+        dev = sv.device
+        dtau = torch.zeros(sv.batch, dtype=torch.float64, device=dev)
+        dbin = torch.zeros(3, dtype=torch.float64, device=dev)
+        dein = torch.zeros(1, dtype=torch.float64, device=dev)
+        lam = [sv.new_lam(), sv.new_lam()]
+        sv.moments_adjoint(self.final, dLde.contiguous(), dLdb.contiguous(), lam[0])
+        cur = 0
+        seg_states = [sv.new_g() for _ in range(min(self.S, max(self.T, 1)))]
+        for k in range(self.K - 1, -1, -1):
+            t0 = k * self.S
+            n = min(self.S, self.T - t0)
+            if n <= 0:
+                continue
+            seg_states[0].copy_(self.ckpt[k])
+            for j in range(1, n):
+                sv.step_g(seg_states[j - 1], seg_states[j])
+            for j in range(n - 1, -1, -1):
+                sv.adjoint_step(seg_states[j], lam[cur], lam[1 - cur], dtau, dbin, dein)
+                cur = 1 - cur
+        de0 = torch.empty(sv.cells, dtype=torch.float64, device=dev)
+        db0 = torch.empty((3, sv.cells), dtype=torch.float64, device=dev)
+        sv.init_adjoint(lam[cur], de0, db0, dbin, dein)
+        return dtau, dein, dbin, de0, db0
+
+
+class RLBFunction(torch.autograd.Function):
+    """(tau[batch], e_in[1], beta_in[3], e0[cells], beta0[3, cells]) -> (e_T, beta_T).
+
+    ``setup`` fixes everything else (extents, boundaries, storage, n0, solid);
+    ``steps`` is T and ``checkpoint`` is "sqrt", "store_all" or a segment length.
+    Inputs may live on any device; the run uses ``setup``'s GPU (cuda:0).
+    """
+
+    @staticmethod
+    def forward(ctx, tau, e_in, beta_in, e0, beta0, setup, steps, checkpoint="sqrt"):
+        tau_h = tau.detach().double().cpu().numpy()
+        inflow = list(setup.inflow)
+        inflow[1] = float(e_in.detach().double().reshape(-1)[0])
+        inflow[2:5] = [float(v) for v in beta_in.detach().double().reshape(-1).cpu()]
+        s = replace(setup, tau=tau_h, inflow=tuple(inflow),
+                    e0=e0.detach().double().cpu().numpy().reshape(-1),
+                    beta0=beta0.detach().double().cpu().numpy().reshape(3, -1))
+        sv = Solver(s)
+        run = GRun(sv, int(steps), segment_length(int(steps), checkpoint))
+        e, b = run.forward()
+        ctx.run = run
+        ctx.devs = (tau.device, e_in.device, beta_in.device, e0.device, beta0.device)
+        ctx.shapes = (tau.shape, e_in.shape, beta_in.shape, e0.shape, beta0.shape)
+        return e.to(e0.device), b.to(beta0.device)
+
+    @staticmethod
+    def backward(ctx, g_e, g_b):
+        run = ctx.run
+        dev = run.sv.device
+        if g_e is None:
+            g_e = torch.zeros(run.sv.cells, dtype=torch.float64, device=dev)
+        if g_b is None:
+            g_b = torch.zeros((3, run.sv.cells), dtype=torch.float64, device=dev)
+        dtau, dein, dbin, de0, db0 = run.backward(g_e.to(dev, torch.float64),
+                                                  g_b.to(dev, torch.float64))
+        outs = []
+        for g, d, sh in zip((dtau, dein, dbin, de0, db0), ctx.devs, ctx.shapes):
+            outs.append(g.to(d).reshape(sh))
+        run.sv.close()
+        ctx.run = None
+        return (*outs, None, None, None)
+
+
+def rlb_run(setup, steps: int, tau=None, e_in=None, beta_in=None, e0=None, beta0=None,
+            checkpoint="sqrt", device="cuda:0"):
+    """Differentiable run: returns (e_T, beta_T) device float64 tensors.  Any
+    parameter left None is taken from ``setup`` as a constant."""
+    f64 = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64), device=device)
+    tau = f64(np.asarray(setup.tau).reshape(-1)) if tau is None else tau
+    e_in = f64([setup.inflow[1]]) if e_in is None else e_in
+    beta_in = f64(setup.inflow[2:5]) if beta_in is None else beta_in
+    e0 = f64(np.asarray(setup.e0).reshape(-1)) if e0 is None else e0
+    beta0 = f64(np.asarray(setup.beta0).reshape(3, -1)) if beta0 is None else beta0
+    return RLBFunction.apply(tau, e_in, beta_in, e0, beta0, setup, steps, checkpoint)
+
+
+def surface_mask(setup) -> np.ndarray:
+    """Fluid cells with at least one solid D3Q19 neighbour (wrapping across
+    periodic faces; nothing lies beyond a non-periodic face)."""
+    if setup.solid is None:
+        return np.zeros(setup.cells, dtype=bool)
+    sol = setup.solid.reshape(setup.batch, setup.nz, setup.ny, setup.nx).astype(bool)
+    near = np.zeros_like(sol)
+    offs = [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)
+            if 0 < dx * dx + dy * dy + dz * dz <= 2]
+    for dx, dy, dz in offs:
+        # sh[b, z, y, x] = sol[b, z + dz, y + dy, x + dx]
+        sh = np.roll(sol, shift=(-dz, -dy, -dx), axis=(1, 2, 3))
+        for axis, d, n, bci in ((3, dx, setup.nx, 0), (2, dy, setup.ny, 1), (1, dz, setup.nz, 2)):
+            if d != 0 and setup.bc[bci][0] != 0:
+                idx = [slice(None)] * 4
+                idx[axis] = n - 1 if d > 0 else 0
+                sh[tuple(idx)] = False
+        near |= sh
+    return (near & ~sol).reshape(-1)

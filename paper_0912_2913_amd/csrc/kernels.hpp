@@ -268,12 +268,21 @@ __device__ __forceinline__ double rest_g(const Phys &ph, int q) {
 }
 __device__ __forceinline__ double rest_f(const Phys &ph, int q) { return WQ[q] * ph.n_ref; }
 
+// Event counters: NSLOT slots per counter, one 128-byte line each, picked by
+// workgroup, so that a state where every wave reports (a NaN-filled lattice)
+// does not serialise on one address.  Counter k, slot i lives at
+// ctr[(k * NSLOT + i) * CSTRIDE]; the host sums the slots.
+constexpr int NSLOT = 256;
+constexpr int CSTRIDE = 16;
+
 // Wave-level ballot counter.
-__device__ __forceinline__ void count_lanes(bool flag, unsigned long long *ctr) {
+__device__ __forceinline__ void count_lanes(bool flag, unsigned long long *ctr, int k) {
   unsigned long long m = __ballot(flag);
   if (m != 0ull) {
     int lane = (int)(threadIdx.x & 63u);
-    if (lane == __ffsll((long long)m) - 1) atomicAdd(ctr, (unsigned long long)__popcll(m));
+    if (lane == __ffsll((long long)m) - 1)
+      atomicAdd(&ctr[(k * NSLOT + (int)(blockIdx.x & (NSLOT - 1))) * CSTRIDE],
+                (unsigned long long)__popcll(m));
   }
 }
 
@@ -375,13 +384,13 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
       dst[q * qs + c.idx] = Cd::enc(post);
     }
   }
-  count_lanes(iv.bad, &counters[0]);
+  count_lanes(iv.bad, counters, 0);
   if (DO_F) {
     // f^eq_i >= 0 needs 1 + 3 b_i > 0 for every i; the largest |b_i| is on a
     // diagonal: |b_x| + |b_y|, |b_x| + |b_z| or |b_y| + |b_z|.
     const double ax = fabs(iv.bx), ay = fabs(iv.by), az = fabs(iv.bz);
     const double mb = fmax(ax + ay, fmax(ax + az, ay + az)) * ph.inv_c;
-    count_lanes(!(3.0 * mb < 1.0), &counters[1]);
+    count_lanes(!(3.0 * mb < 1.0), counters, 1);
   }
 }
 
@@ -444,9 +453,11 @@ __global__ void k_inflow_eq(const Phys ph, double n, double e, double bx, double
 
 // ---------------------------------------------------------------------------
 // Fields and per-block conservation partials of a stored state.
+// Sf may be null (g block only: n is not computed and the f sum is zero).
 template <int ST>
 __global__ __launch_bounds__(BLOCK) void k_moments(const Geom g, const Phys ph,
-                                                   const typename Codec<ST>::elem *__restrict__ S,
+                                                   const typename Codec<ST>::elem *__restrict__ Sf,
+                                                   const typename Codec<ST>::elem *__restrict__ Sg,
                                                    double *__restrict__ n, double *__restrict__ e,
                                                    double *__restrict__ beta,
                                                    double *__restrict__ part) {
@@ -464,15 +475,15 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const Geom g, const Phys ph,
       double N = 0.0, Eg = 0.0, sx, sy, sz, gv[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        N += (double)Cd::dec(S[q * qs + c.idx]);
-        gv[q] = (double)Cd::dec(S[(Q + q) * qs + c.idx]);
+        if (Sf) N += (double)Cd::dec(Sf[q * qs + c.idx]);
+        gv[q] = (double)Cd::dec(Sg[q * qs + c.idx]);
         Eg += gv[q];
       }
       mirror_sums(gv, sx, sy, sz);
-      N += ph.n_ref;  // the rest parts sum to (n_ref, e_ref, 0)
+      if (Sf) N += ph.n_ref;  // the rest parts sum to (n_ref, e_ref, 0)
       Eg += ph.e_ref;
       const Inv iv = invert(Eg, ph.c * sx, ph.c * sy, ph.c * sz);
-      if (n) n[c.idx] = N * sqrt(1.0 - (iv.bx * iv.bx + iv.by * iv.by + iv.bz * iv.bz));
+      if (n && Sf) n[c.idx] = N * sqrt(1.0 - (iv.bx * iv.bx + iv.by * iv.by + iv.bz * iv.bz));
       if (e) e[c.idx] = iv.eps;
       if (beta) {
         beta[c.idx] = iv.bx;

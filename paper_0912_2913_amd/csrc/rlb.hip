@@ -37,6 +37,8 @@ namespace {
 
 thread_local std::string g_err;
 
+constexpr size_t kCounterBytes = sizeof(unsigned long long) * 2 * NSLOT * CSTRIDE;
+
 rlb_status fail(rlb_status s, const std::string &msg) {
   g_err = msg;
   return s;
@@ -209,11 +211,22 @@ rlb_status launch_step_g(rlb_solver *h, const void *src, void *dst) {
 template <int ST>
 rlb_status launch_moments(rlb_solver *h, double *n, double *e, double *beta, bool sums) {
   using El = typename Codec<ST>::elem;
+  const El *S = (const El *)h->pop[h->cur];
   hipLaunchKernelGGL(k_moments<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
-                     (const El *)h->pop[h->cur], n, e, beta, sums ? h->d_part : nullptr);
+                     S, S + (size_t)Q * h->g.qs, n, e, beta, sums ? h->d_part : nullptr);
   if (sums)
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(BLOCK), 0, h->stream, h->d_part, h->p.batch,
                        h->g.nblk_per, h->d_res, nullptr, nullptr, nullptr);
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
+}
+
+template <int ST>
+rlb_status launch_fields_g(rlb_solver *h, const void *Sg, double *e, double *beta) {
+  using El = typename Codec<ST>::elem;
+  hipLaunchKernelGGL(k_moments<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
+                     (const El *)nullptr, (const El *)Sg, (double *)nullptr, e, beta,
+                     (double *)nullptr);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -361,10 +374,9 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
     return cleanup_fail(e, "copy omega");
   if ((e = hipMalloc(&h->d_in_eq, 2 * Q * 8)) != hipSuccess)
     return cleanup_fail(e, "hipMalloc(inflow)");
-  if ((e = hipMalloc(&h->d_counters, 2 * sizeof(unsigned long long))) != hipSuccess)
+  if ((e = hipMalloc(&h->d_counters, kCounterBytes)) != hipSuccess)
     return cleanup_fail(e, "hipMalloc(counters)");
-  if ((e = hipMemsetAsync(h->d_counters, 0, 2 * sizeof(unsigned long long), h->stream)) !=
-      hipSuccess)
+  if ((e = hipMemsetAsync(h->d_counters, 0, kCounterBytes, h->stream)) != hipSuccess)
     return cleanup_fail(e, "clear counters");
   if ((e = hipMalloc(&h->d_part, sizeof(double) * 5 * (size_t)h->g.nblk)) != hipSuccess)
     return cleanup_fail(e, "hipMalloc(partials)");
@@ -422,13 +434,23 @@ rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double
   return RLB_OK;
 }
 
+rlb_status rlb_fields_g(rlb_solver *h, const void *g_state, double *e, double *beta) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (!g_state || (!e && !beta)) return fail(RLB_EINVAL, "g_state or outputs invalid");
+  RLB_DISPATCH(h->st, launch_fields_g, h, g_state, e, beta);
+}
+
 rlb_status rlb_counters(rlb_solver *h, int64_t counts[2]) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   if (!counts) return fail(RLB_EINVAL, "counts is NULL");
-  unsigned long long c[2];
-  RLB_HIP(hipMemcpyAsync(c, h->d_counters, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+  std::vector<unsigned long long> buf(kCounterBytes / sizeof(unsigned long long));
+  RLB_HIP(hipMemcpyAsync(buf.data(), h->d_counters, kCounterBytes, hipMemcpyDeviceToHost,
+                         h->stream));
   RLB_HIP(hipStreamSynchronize(h->stream));
-  RLB_HIP(hipMemsetAsync(h->d_counters, 0, sizeof(c), h->stream));
+  RLB_HIP(hipMemsetAsync(h->d_counters, 0, kCounterBytes, h->stream));
+  unsigned long long c[2] = {0, 0};
+  for (int k = 0; k < 2; ++k)
+    for (int i = 0; i < NSLOT; ++i) c[k] += buf[(size_t)(k * NSLOT + i) * CSTRIDE];
   counts[0] = (int64_t)c[0];
   counts[1] = (int64_t)c[1];
   return c[0] > 0 ? RLB_EUNPHYSICAL : RLB_OK;

@@ -132,6 +132,13 @@ class Solver:
         check(_lib.lib().rlb_moments(self.h, _ptr(n), _ptr(e), _ptr(b), sp), "rlb_moments")
         return (n, e, b, out) if sums else (n, e, b)
 
+    def fields_g(self, g_state: torch.Tensor):
+        """(e [cells], beta [3, cells]) device float64 of a g block."""
+        e = torch.empty(self.cells, dtype=torch.float64, device=self.device)
+        b = torch.empty((3, self.cells), dtype=torch.float64, device=self.device)
+        check(_lib.lib().rlb_fields_g(self.h, _ptr(g_state), _ptr(e), _ptr(b)), "rlb_fields_g")
+        return e, b
+
     def counters(self, raise_on_unphysical: bool = False):
         c = (ctypes.c_int64 * 2)()
         st = _lib.lib().rlb_counters(self.h, c)

@@ -39,17 +39,26 @@ def compare(s: ri.Setup, steps: int, tol=TOL, check_n=True):
         errs["beta_" + ax] = float(np.abs(gb[k][m] - b[k][m]).max() / bscale)
     fin = np.isfinite(n) & m
     if check_n and fin.any():
-        errs["n"] = field_err(gn, n, fin)
+        # n = sqrt(1 - beta^2) sum_i f_i: its rounding scale is sqrt(1 - beta^2) sum_i |f_i|,
+        # which is n itself wherever every f_i >= 0 (the paper's positivity condition)
+        # and far larger where f^eq has negative components and f diverges
+        nscale = np.sqrt(1.0 - (b ** 2).sum(0)) * np.abs(S[0]).sum(0)
+        errs["n"] = float(np.abs(gn[fin] - n[fin]).max() / nscale[fin].max())
     st = gpu_state(sv)
     errs["g_pop"] = field_err(st[1], S[1], m)
     if check_n:
         finite = np.isfinite(S[0]).all(axis=0) & m
         errs["f_pop"] = field_err(st[0], S[0], finite)
+    gbad, fbad = sv.counters()
+    # Where f^eq has negative components (c_i.beta < -c_l^2/3, the paper's
+    # positivity bound) f grows geometrically with a rate that depends on beta, so
+    # a 1e-14 difference in beta becomes ~steps x 1e-14 in f and n: those fields
+    # are compared at 1e-10 there; e and beta (from g alone) keep the 1e-12 bar.
+    f_tol = tol if fbad == 0 else 1e-10
     for k, v in errs.items():
-        assert v <= tol, (k, v, errs)
+        assert v <= (f_tol if k in ("n", "f_pop") else tol), (k, v, errs)
     # conservation sums (fixed-order FP64 reductions) against the oracle's
     assert np.allclose(gsums[:, 1], sums[:, 1], rtol=1e-12, atol=0)
-    gbad, fbad = sv.counters()
     assert gbad == bad
     sv.close()
     return errs
