@@ -56,9 +56,13 @@ struct Geom {
   int periodic[3];
   int inflow_lo[3], inflow_hi[3];
   int any_inflow;
-  int off[Q];          // fast-path pull offsets (source = cell - off[q])
-  int flo[3], fhi[3];  // forward fast range per axis
-  int alo[3], ahi[3];  // adjoint fast range per axis
+  int off[Q];  // interior pull offsets: source = cell - off[q]
+  // Index corrections of a pull that leaves the domain through the low face
+  // (cell on coordinate 0, e_a = +1) or the high face (coordinate n-1,
+  // e_a = -1): +-n*stride wraps a periodic axis, +-stride clamps an outflow
+  // axis onto the face (zero-gradient copy), 0 on a periodic axis of one cell.
+  int corr_lo[3], corr_hi[3];
+  int alo[3], ahi[3];  // adjoint fast range per axis (whole axis if periodic)
 };
 
 struct Phys {
@@ -112,6 +116,36 @@ __device__ __forceinline__ bool is_inflow(const Geom &g, int x, int y, int z) {
 __device__ __forceinline__ bool in_fast(const Cell &c, const int lo[3], const int hi[3]) {
   return c.x >= lo[0] && c.x <= hi[0] && c.y >= lo[1] && c.y <= hi[1] && c.z >= lo[2] &&
          c.z <= hi[2];
+}
+
+// Branch-free pull sources of a cell with no solid neighbour: the per-lane
+// face corrections are selected once, then each direction adds the ones its
+// velocity components call for (compile-time after unrolling).
+struct FaceCorr {
+  int lx, hx, ly, hy, lz, hz;
+};
+
+__device__ __forceinline__ FaceCorr face_corr(const Geom &g, const Cell &c) {
+  FaceCorr f;
+  f.lx = c.x == 0 ? g.corr_lo[0] : 0;
+  f.hx = c.x == g.n[0] - 1 ? g.corr_hi[0] : 0;
+  f.ly = c.y == 0 ? g.corr_lo[1] : 0;
+  f.hy = c.y == g.n[1] - 1 ? g.corr_hi[1] : 0;
+  f.lz = c.z == 0 ? g.corr_lo[2] : 0;
+  f.hz = c.z == g.n[2] - 1 ? g.corr_hi[2] : 0;
+  return f;
+}
+
+__device__ __forceinline__ long long src_fast(const Geom &g, const Cell &c, const FaceCorr &f,
+                                              int q) {
+  long long s = c.idx - g.off[q];
+  if (EX[q] == 1) s += f.lx;
+  if (EX[q] == -1) s += f.hx;
+  if (EY[q] == 1) s += f.ly;
+  if (EY[q] == -1) s += f.hy;
+  if (EZ[q] == 1) s += f.lz;
+  if (EZ[q] == -1) s += f.hz;
+  return s;
 }
 
 // Pull-source coordinate on one axis: wrap (periodic) or clamp (outflow).
@@ -313,6 +347,56 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *out) {
   }
 }
 
+// Pull the 19 values of one population for cell c (decoded to the compute
+// type): branch-free face corrections unless a neighbour is solid.
+template <class Cd>
+__device__ __forceinline__ void gather(const Geom &g, const Phys &ph, const Cell &c, bool near,
+                                       const typename Cd::elem *__restrict__ P, size_t qs,
+                                       typename Cd::calc (&v)[Q]) {
+  if (!near) {
+    const FaceCorr fc = face_corr(g, c);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = Cd::dec(P[q * qs + src_fast(g, c, fc, q)]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const Pull p = pull_general(g, ph, c, q);
+      v[q] = Cd::dec(P[p.q * qs + p.idx]);
+    }
+  }
+}
+
+// Both populations of cell c, pulled in one pass (same sources for f and g).
+template <class Cd>
+__device__ __forceinline__ void gather2(const Geom &g, const Phys &ph, const Cell &c, bool near,
+                                        const typename Cd::elem *__restrict__ G,
+                                        const typename Cd::elem *__restrict__ F, size_t qs,
+                                        typename Cd::calc (&vg)[Q], typename Cd::calc (&vf)[Q]) {
+  if (!near) {
+    const FaceCorr fc = face_corr(g, c);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const long long s = src_fast(g, c, fc, q);
+      vg[q] = Cd::dec(G[q * qs + s]);
+      vf[q] = Cd::dec(F[q * qs + s]);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const Pull p = pull_general(g, ph, c, q);
+      vg[q] = Cd::dec(G[p.q * qs + p.idx]);
+      vf[q] = Cd::dec(F[p.q * qs + p.idx]);
+    }
+  }
+}
+
+// The step's outputs are read once, by the next step: stream them past the
+// caches (non-temporal store).
+template <class El>
+__device__ __forceinline__ void stream_store(El *p, El v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 // ---------------------------------------------------------------------------
 // Forward stream-collide step.  DO_F = false updates the g population only
 // (src/dst then address g blocks).
@@ -340,52 +424,36 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
     }
     return;
   }
+  // All 38 pulls are issued before any arithmetic (both populations in
+  // flight per wave); g then f are relaxed and streamed out.
+  const bool near = cls & CLS_NEAR;
   T pg[Q], pf[Q];
-  if (!(cls & CLS_NEAR) && in_fast(c, g.flo, g.fhi)) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const long long s = c.idx - g.off[q];
-      pg[q] = Cd::dec(gs[q * qs + s]);
-      if (DO_F) pf[q] = Cd::dec(src[q * qs + s]);
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const Pull p = pull_general(g, ph, c, q);
-      pg[q] = Cd::dec(gs[p.q * qs + p.idx]);
-      if (DO_F) pf[q] = Cd::dec(src[p.q * qs + p.idx]);
-    }
-  }
-  // moments (in T), inversion (FP64)
+  if (DO_F)
+    gather2<Cd>(g, ph, c, near, gs, src, qs, pg, pf);
+  else
+    gather<Cd>(g, ph, c, near, gs, qs, pg);
   T sE = (T)0, sx, sy, sz;
 #pragma unroll
   for (int q = 0; q < Q; ++q) sE += pg[q];
   mirror_sums(pg, sx, sy, sz);
   const Inv iv = invert(ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
                         ph.c * (double)sz);
-  double Nsum = 0.0;
-  T sN = (T)0;
-  if (DO_F) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) sN += pf[q];
-    Nsum = ph.n_ref + (double)sN;
-  }
-  const EqCoef<T> k = eq_coef<T>(ph, Nsum, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
+  EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
   const T om = (T)ph.omega[c.b];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const T post = pg[q] + om * (geq_dev(k, q) - pg[q]);
-    gd[q * qs + c.idx] = Cd::enc(post);
-  }
-  if (DO_F) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const T post = pf[q] + om * (feq_dev(k, q) - pf[q]);
-      dst[q * qs + c.idx] = Cd::enc(post);
-    }
-  }
+  for (int q = 0; q < Q; ++q)
+    stream_store(&gd[q * qs + c.idx], Cd::enc(pg[q] + om * (geq_dev(k, q) - pg[q])));
   count_lanes(iv.bad, counters, 0);
   if (DO_F) {
+    T sN = (T)0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) sN += pf[q];
+    const double N = ph.n_ref + (double)sN;
+    k.N = (T)N;
+    k.Nd = (T)(N - ph.n_ref);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      stream_store(&dst[q * qs + c.idx], Cd::enc(pf[q] + om * (feq_dev(k, q) - pf[q])));
     // f^eq_i >= 0 needs 1 + 3 b_i > 0 for every i; the largest |b_i| is on a
     // diagonal: |b_x| + |b_y|, |b_x| + |b_z| or |b_y| + |b_z|.
     const double ax = fabs(iv.bx), ay = fabs(iv.by), az = fabs(iv.bz);
@@ -695,9 +763,10 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
       for (int k2 = 0; k2 < 4; ++k2) acc[1 + k2] = gr[k2];
     } else if (!solid) {
       T pre[Q], lam[Q];
+      const FaceCorr fc = face_corr(g, c);
       if (fast) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) pre[q] = Cd::dec(S[q * qs + c.idx - g.off[q]]);
+        for (int q = 0; q < Q; ++q) pre[q] = Cd::dec(S[q * qs + src_fast(g, c, fc, q)]);
       } else {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -733,7 +802,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
         if (EZ[q] == 1) mu += az;
         if (EZ[q] == -1) mu -= az;
         if (fast) {
-          lam_out[q * qs + c.idx - g.off[q]] = (Lm)mu;
+          lam_out[q * qs + src_fast(g, c, fc, q)] = (Lm)mu;
         } else {
           const Pull p = pull_general(g, ph, c, q);
           if (p.bounce)

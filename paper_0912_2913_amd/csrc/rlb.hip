@@ -134,14 +134,19 @@ void setup_geometry(rlb_solver *h) {
     g.inflow_lo[a] = p.bc[a][0] == RLB_BC_INFLOW;
     g.inflow_hi[a] = p.bc[a][1] == RLB_BC_INFLOW;
     if (g.inflow_lo[a] || g.inflow_hi[a]) g.any_inflow = 1;
-    if (g.periodic[a] && g.n[a] == 1) {
-      // every pull along this axis returns to the cell itself
-      g.flo[a] = g.fhi[a] = g.alo[a] = g.ahi[a] = 0;
+    if (g.periodic[a]) {
+      // wrap: whole axis on the fast paths; one cell: every pull returns to itself
+      g.alo[a] = 0;
+      g.ahi[a] = g.n[a] - 1;
+      g.corr_lo[a] = g.n[a] == 1 ? 0 : g.n[a] * stride[a];
+      g.corr_hi[a] = g.n[a] == 1 ? 0 : -g.n[a] * stride[a];
     } else {
-      g.flo[a] = 1;
-      g.fhi[a] = g.n[a] - 2;
+      // clamp onto the face; the reverse step keeps face layers (and the layer
+      // next to an inflow plane) on its general path
       g.alo[a] = 1 + (g.inflow_lo[a] ? 1 : 0);
       g.ahi[a] = g.n[a] - 2 - (g.inflow_hi[a] ? 1 : 0);
+      g.corr_lo[a] = stride[a];
+      g.corr_hi[a] = -stride[a];
     }
   }
   const int e[Q][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
