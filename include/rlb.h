@@ -70,6 +70,12 @@ typedef enum {
   RLB_BF16DEV = 4
 } rlb_storage;
 
+/* Type of the collision arithmetic (moment sums, equilibria, relaxation); the
+ * moment inversion is FP64 always.  AUTO = FP64 for RLB_F64/F32/F32DEV and
+ * FP32 for the 16-bit storages.  FP32 collision is not offered with RLB_F64
+ * storage, nor FP64 collision with 16-bit storage. */
+typedef enum { RLB_COLLIDE_AUTO = 0, RLB_COLLIDE_F32 = 1, RLB_COLLIDE_F64 = 2 } rlb_collide;
+
 /* Problem statement (shock-tube and obstacle sections of the paper: domain,
  * lattice speed c_l, fixed obstacle, inflow state; e = 3P is built in). */
 typedef struct {
@@ -80,6 +86,7 @@ typedef struct {
   double inflow_beta[3];
   int32_t storage;           /* rlb_storage                                      */
   double n_ref, e_ref;       /* rest reference of the *DEV storages              */
+  int32_t collide;           /* rlb_collide                                      */
 } rlb_params;
 
 /* Layout of one population buffer for these parameters: q_stride elements per

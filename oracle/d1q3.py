@@ -53,8 +53,11 @@ def invert(F, G, c_l):
 
 def run(n0, e0, beta0, tau, c_l, nsteps, bc="outflow"):
     """Run nsteps on a line of nz cells; returns (n, e, beta) at the end.
-    bc = 'outflow' (zero-gradient copy at both ends) or 'periodic'."""
-    F, G = equilibria(np.asarray(n0, float), np.asarray(e0, float), np.asarray(beta0, float), c_l)
+    bc = 'outflow' (zero-gradient copy at both ends) or 'periodic'.  Every
+    operation is analytic, so complex inputs (tau + i h, e0 + i h v) give
+    complex-step derivatives."""
+    as_arr = lambda a: np.asarray(a) if np.iscomplexobj(a) else np.asarray(a, float)
+    F, G = equilibria(as_arr(n0), as_arr(e0), as_arr(beta0), c_l)
     om = 1.0 / tau
     for _ in range(nsteps):
         # pull streaming: + group comes from z-1, - group from z+1

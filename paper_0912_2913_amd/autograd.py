@@ -49,17 +49,18 @@ class GRun:
         self.ckpt: List[torch.Tensor] = []
         self.final: Optional[torch.Tensor] = None
 
-    def forward(self):
+    def forward(self, keep: bool = True):
+        """Run the T steps; with keep=False no checkpoint is stored (no reverse)."""
         sv = self.sv
         a = sv.g_state().clone()  # S_0
         b = sv.new_g()
         self.ckpt = []
         for t in range(self.T):
-            if t % self.S == 0:
+            if keep and t % self.S == 0:
                 self.ckpt.append(a.clone())
             sv.step_g(a, b)
             a, b = b, a
-        if self.T == 0:
+        if keep and self.T == 0:
             self.ckpt.append(a.clone())
         self.final = a
         return sv.fields_g(a)
@@ -110,7 +111,11 @@ class RLBFunction(torch.autograd.Function):
                     beta0=beta0.detach().double().cpu().numpy().reshape(3, -1))
         sv = Solver(s)
         run = GRun(sv, int(steps), segment_length(int(steps), checkpoint))
-        e, b = run.forward()
+        need = any(ctx.needs_input_grad[:5])
+        e, b = run.forward(keep=need)
+        if not need:
+            sv.close()
+            run = None
         ctx.run = run
         ctx.devs = (tau.device, e_in.device, beta_in.device, e0.device, beta0.device)
         ctx.shapes = (tau.shape, e_in.shape, beta_in.shape, e0.shape, beta0.shape)

@@ -1,7 +1,10 @@
-// Population storage formats.  F64 and F32 store S_i itself.  The *DEV forms
-// store the deviation d_i = S_i - R_i from the rest equilibrium R at
-// (n_ref, e_ref); the collision then works on deviations in FP32 and the
-// rest part never enters the rounding.
+// Population storage formats and the collision's compute type.
+//
+// F64 and F32 store S_i itself.  The *DEV forms store the deviation
+// d_i = S_i - R_i from the rest equilibrium R at (n_ref, e_ref); the collision
+// then works on deviations and the rest part never enters the rounding.  The
+// compute type TC (double or float) is the type of the moment sums, the
+// equilibria and the relaxation; the moment inversion is FP64 in every case.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,50 +13,6 @@
 namespace rlb {
 
 enum { ST_F64 = 0, ST_F32 = 1, ST_F32DEV = 2, ST_F16DEV = 3, ST_BF16DEV = 4 };
-
-template <int ST>
-struct Codec;
-
-template <>
-struct Codec<ST_F64> {
-  using elem = double;
-  using calc = double;
-  using lam = double;
-  static constexpr bool dev = false;
-  __device__ static calc dec(elem v) { return v; }
-  __device__ static elem enc(calc v) { return v; }
-};
-
-template <>
-struct Codec<ST_F32> {
-  using elem = float;
-  using calc = float;
-  using lam = float;
-  static constexpr bool dev = false;
-  __device__ static calc dec(elem v) { return v; }
-  __device__ static elem enc(calc v) { return v; }
-};
-
-template <>
-struct Codec<ST_F32DEV> {
-  using elem = float;
-  using calc = float;
-  using lam = float;
-  static constexpr bool dev = true;
-  __device__ static calc dec(elem v) { return v; }
-  __device__ static elem enc(calc v) { return v; }
-};
-
-template <>
-struct Codec<ST_F16DEV> {
-  using elem = _Float16;
-  using calc = float;
-  using lam = float;
-  static constexpr bool dev = true;
-  __device__ static calc dec(elem v) { return (float)v; }
-  // hardware conversion, round-to-nearest-even (the default rounding mode)
-  __device__ static elem enc(calc v) { return (_Float16)v; }
-};
 
 // bfloat16 = the upper 16 bits of an IEEE binary32.  Encoding rounds to
 // nearest, ties to even, on the discarded 16 bits; NaNs stay (quiet) NaNs.
@@ -64,14 +23,69 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
+template <int ST>
+struct Format;
+
 template <>
-struct Codec<ST_BF16DEV> {
-  using elem = uint16_t;
-  using calc = float;
+struct Format<ST_F64> {
+  using elem = double;
+  using lam = double;  // adjoint buffers
+  static constexpr bool dev = false;
+  template <class T>
+  __device__ static T dec(elem v) { return (T)v; }
+  template <class T>
+  __device__ static elem enc(T v) { return (elem)v; }
+};
+
+template <>
+struct Format<ST_F32> {
+  using elem = float;
+  using lam = float;
+  static constexpr bool dev = false;
+  template <class T>
+  __device__ static T dec(elem v) { return (T)v; }
+  // one rounding (round to nearest even) from the compute type
+  template <class T>
+  __device__ static elem enc(T v) { return (elem)v; }
+};
+
+template <>
+struct Format<ST_F32DEV> : Format<ST_F32> {
+  static constexpr bool dev = true;
+};
+
+template <>
+struct Format<ST_F16DEV> {
+  using elem = _Float16;
   using lam = float;
   static constexpr bool dev = true;
-  __device__ static calc dec(elem v) { return __uint_as_float((uint32_t)v << 16); }
-  __device__ static elem enc(calc v) { return f32_to_bf16_rne(v); }
+  template <class T>
+  __device__ static T dec(elem v) { return (T)(float)v; }
+  // hardware conversion, round to nearest even (the default rounding mode);
+  // only FP32 compute is paired with this format
+  __device__ static elem enc(float v) { return (_Float16)v; }
+};
+
+template <>
+struct Format<ST_BF16DEV> {
+  using elem = uint16_t;
+  using lam = float;
+  static constexpr bool dev = true;
+  template <class T>
+  __device__ static T dec(elem v) { return (T)__uint_as_float((uint32_t)v << 16); }
+  // only FP32 compute is paired with this format
+  __device__ static elem enc(float v) { return f32_to_bf16_rne(v); }
+};
+
+template <int ST, class TC>
+struct Codec {
+  using F = Format<ST>;
+  using elem = typename F::elem;
+  using calc = TC;
+  using lam = typename F::lam;
+  static constexpr bool dev = F::dev;
+  __device__ static calc dec(elem v) { return F::template dec<calc>(v); }
+  __device__ static elem enc(calc v) { return F::enc(v); }
 };
 
 }  // namespace rlb

@@ -400,13 +400,13 @@ __device__ __forceinline__ void stream_store(El *p, El v) {
 // ---------------------------------------------------------------------------
 // Forward stream-collide step.  DO_F = false updates the g population only
 // (src/dst then address g blocks).
-template <int ST, bool DO_F>
+template <int ST, class TC, bool DO_F>
 __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
-                                                const typename Codec<ST>::elem *__restrict__ src,
-                                                typename Codec<ST>::elem *__restrict__ dst,
-                                                const typename Codec<ST>::elem *__restrict__ in_eq,
+                                                const typename Codec<ST, TC>::elem *__restrict__ src,
+                                                typename Codec<ST, TC>::elem *__restrict__ dst,
+                                                const typename Codec<ST, TC>::elem *__restrict__ in_eq,
                                                 unsigned long long *__restrict__ counters) {
-  using Cd = Codec<ST>;
+  using Cd = Codec<ST, TC>;
   using T = typename Cd::calc;
   using El = typename Cd::elem;
   const Cell c = decode_cell(g);
@@ -465,15 +465,15 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
 // ---------------------------------------------------------------------------
 // Initial state: equilibria of (n0, e0, beta0); inflow cells take the inflow
 // equilibrium; solid cells hold zeros in both buffers.
-template <int ST>
+template <int ST, class TC>
 __global__ __launch_bounds__(BLOCK) void k_init(const Geom g, const Phys ph,
                                                 const double *__restrict__ n0,
                                                 const double *__restrict__ e0,
                                                 const double *__restrict__ beta0,
-                                                typename Codec<ST>::elem *__restrict__ pa,
-                                                typename Codec<ST>::elem *__restrict__ pb,
-                                                const typename Codec<ST>::elem *__restrict__ in_eq) {
-  using Cd = Codec<ST>;
+                                                typename Codec<ST, TC>::elem *__restrict__ pa,
+                                                typename Codec<ST, TC>::elem *__restrict__ pb,
+                                                const typename Codec<ST, TC>::elem *__restrict__ in_eq) {
+  using Cd = Codec<ST, TC>;
   using T = typename Cd::calc;
   const Cell c = decode_cell(g);
   if (!c.active) return;
@@ -505,10 +505,10 @@ __global__ __launch_bounds__(BLOCK) void k_init(const Geom g, const Phys ph,
 }
 
 // Inflow equilibrium (38 values in storage format), one thread.
-template <int ST>
+template <int ST, class TC>
 __global__ void k_inflow_eq(const Phys ph, double n, double e, double bx, double by, double bz,
-                            typename Codec<ST>::elem *__restrict__ out) {
-  using Cd = Codec<ST>;
+                            typename Codec<ST, TC>::elem *__restrict__ out) {
+  using Cd = Codec<ST, TC>;
   using T = typename Cd::calc;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const double g2 = 1.0 / (1.0 - (bx * bx + by * by + bz * bz));
@@ -522,14 +522,14 @@ __global__ void k_inflow_eq(const Phys ph, double n, double e, double bx, double
 // ---------------------------------------------------------------------------
 // Fields and per-block conservation partials of a stored state.
 // Sf may be null (g block only: n is not computed and the f sum is zero).
-template <int ST>
+template <int ST, class TC>
 __global__ __launch_bounds__(BLOCK) void k_moments(const Geom g, const Phys ph,
-                                                   const typename Codec<ST>::elem *__restrict__ Sf,
-                                                   const typename Codec<ST>::elem *__restrict__ Sg,
+                                                   const typename Codec<ST, TC>::elem *__restrict__ Sf,
+                                                   const typename Codec<ST, TC>::elem *__restrict__ Sg,
                                                    double *__restrict__ n, double *__restrict__ e,
                                                    double *__restrict__ beta,
                                                    double *__restrict__ part) {
-  using Cd = Codec<ST>;
+  using Cd = Codec<ST, TC>;
   const Cell c = decode_cell(g);
   const size_t qs = (size_t)g.qs;
   const size_t cells = (size_t)g.batch * g.per;
@@ -729,13 +729,13 @@ __device__ __forceinline__ bool covered(const Geom &g, const Phys &ph, const Cel
 // lambda_t for every direction of every cell except the clamped-pull
 // contributions, which go to `scratch` (indexed by the reading cell) and are
 // added by k_adjoint_faces.  part[L][5] = (dtau, de_in, dbeta_in[3]) partials.
-template <int ST>
+template <int ST, class TC>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(
-    const Geom g, const Phys ph, const typename Codec<ST>::elem *__restrict__ S,
-    const typename Codec<ST>::lam *__restrict__ lam_next,
-    typename Codec<ST>::lam *__restrict__ lam_out, typename Codec<ST>::lam *__restrict__ scratch,
+    const Geom g, const Phys ph, const typename Codec<ST, TC>::elem *__restrict__ S,
+    const typename Codec<ST, TC>::lam *__restrict__ lam_next,
+    typename Codec<ST, TC>::lam *__restrict__ lam_out, typename Codec<ST, TC>::lam *__restrict__ scratch,
     double *__restrict__ part, const InflowState in) {
-  using Cd = Codec<ST>;
+  using Cd = Codec<ST, TC>;
   using T = typename Cd::calc;
   using Lm = typename Cd::lam;
   const Cell c = decode_cell(g);
@@ -905,12 +905,12 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_faces(const Geom g, const Phy
 }
 
 // lambda_T = (d(e, beta)/d S_T)^T (dL/de, dL/dbeta), cell-local.
-template <int ST>
+template <int ST, class TC>
 __global__ __launch_bounds__(BLOCK) void k_moments_adjoint(
-    const Geom g, const Phys ph, const typename Codec<ST>::elem *__restrict__ S,
+    const Geom g, const Phys ph, const typename Codec<ST, TC>::elem *__restrict__ S,
     const double *__restrict__ dLde, const double *__restrict__ dLdb,
-    typename Codec<ST>::lam *__restrict__ lam) {
-  using Cd = Codec<ST>;
+    typename Codec<ST, TC>::lam *__restrict__ lam) {
+  using Cd = Codec<ST, TC>;
   using Lm = typename Cd::lam;
   const Cell c = decode_cell(g);
   if (!c.active) return;
@@ -938,12 +938,12 @@ __global__ __launch_bounds__(BLOCK) void k_moments_adjoint(
 }
 
 // lambda_0 -> dL/de0, dL/dbeta0 (overwritten) and inflow partials.
-template <int ST>
+template <int ST, class TC>
 __global__ __launch_bounds__(BLOCK) void k_init_adjoint(
     const Geom g, const Phys ph, const double *__restrict__ e0, const double *__restrict__ beta0,
-    const typename Codec<ST>::lam *__restrict__ lam0, double *__restrict__ de0,
+    const typename Codec<ST, TC>::lam *__restrict__ lam0, double *__restrict__ de0,
     double *__restrict__ db0, double *__restrict__ part, const InflowState in) {
-  using Cd = Codec<ST>;
+  using Cd = Codec<ST, TC>;
   using T = typename Cd::calc;
   const Cell c = decode_cell(g);
   const size_t qs = (size_t)g.qs;

@@ -19,7 +19,7 @@ struct rlb_solver {
   Phys ph;
   InflowState in;
   Faces faces;
-  int st;
+  int st, cp;
   size_t elem, lam_elem;
   void *pop[2];
   int cur;
@@ -105,6 +105,13 @@ rlb_status validate(const rlb_params *p, long long *cells_out) {
     if (!std::isfinite(p->inflow_n)) return fail(RLB_EINVAL, "inflow_n must be finite");
   }
   if (elem_size(p->storage) == 0) return fail(RLB_EINVAL, "unknown storage");
+  if (p->collide != RLB_COLLIDE_AUTO && p->collide != RLB_COLLIDE_F32 &&
+      p->collide != RLB_COLLIDE_F64)
+    return fail(RLB_EINVAL, "unknown collision type");
+  if (p->storage == RLB_F64 && p->collide == RLB_COLLIDE_F32)
+    return fail(RLB_EINVAL, "FP64 storage collides in FP64");
+  if ((p->storage == RLB_F16DEV || p->storage == RLB_BF16DEV) && p->collide == RLB_COLLIDE_F64)
+    return fail(RLB_EINVAL, "16-bit storages collide in FP32");
   if (p->storage >= ST_F32DEV) {
     if (!(p->e_ref > 0.0) || !std::isfinite(p->e_ref) || !std::isfinite(p->n_ref))
       return fail(RLB_EINVAL, "deviation storage needs e_ref > 0 and finite n_ref");
@@ -178,24 +185,24 @@ void setup_geometry(rlb_solver *h) {
 
 unsigned grid_blocks(const rlb_solver *h) { return (unsigned)h->g.nblk; }
 
-template <int ST>
+template <int ST, class TC>
 rlb_status launch_init(rlb_solver *h, const double *n0, const double *e0, const double *beta0) {
-  using El = typename Codec<ST>::elem;
+  using El = typename Codec<ST, TC>::elem;
   const rlb_params &p = h->p;
-  hipLaunchKernelGGL(k_inflow_eq<ST>, dim3(1), dim3(64), 0, h->stream, h->ph, p.inflow_n,
+  hipLaunchKernelGGL((k_inflow_eq<ST, TC>), dim3(1), dim3(64), 0, h->stream, h->ph, p.inflow_n,
                      p.inflow_e, p.inflow_beta[0], p.inflow_beta[1], p.inflow_beta[2],
                      (El *)h->d_in_eq);
-  hipLaunchKernelGGL(k_init<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
+  hipLaunchKernelGGL((k_init<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
                      n0, e0, beta0, (El *)h->pop[0], (El *)h->pop[1], (const El *)h->d_in_eq);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
 
-template <int ST>
+template <int ST, class TC>
 rlb_status launch_steps(rlb_solver *h, int nsteps) {
-  using El = typename Codec<ST>::elem;
+  using El = typename Codec<ST, TC>::elem;
   for (int s = 0; s < nsteps; ++s) {
-    hipLaunchKernelGGL((k_step<ST, true>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+    hipLaunchKernelGGL((k_step<ST, TC, true>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
                        h->ph, (const El *)h->pop[h->cur], (El *)h->pop[1 - h->cur],
                        (const El *)h->d_in_eq, h->d_counters);
     h->cur = 1 - h->cur;
@@ -204,20 +211,20 @@ rlb_status launch_steps(rlb_solver *h, int nsteps) {
   return RLB_OK;
 }
 
-template <int ST>
+template <int ST, class TC>
 rlb_status launch_step_g(rlb_solver *h, const void *src, void *dst) {
-  using El = typename Codec<ST>::elem;
-  hipLaunchKernelGGL((k_step<ST, false>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+  using El = typename Codec<ST, TC>::elem;
+  hipLaunchKernelGGL((k_step<ST, TC, false>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
                      h->ph, (const El *)src, (El *)dst, (const El *)h->d_in_eq, h->d_counters);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
 
-template <int ST>
+template <int ST, class TC>
 rlb_status launch_moments(rlb_solver *h, double *n, double *e, double *beta, bool sums) {
-  using El = typename Codec<ST>::elem;
+  using El = typename Codec<ST, TC>::elem;
   const El *S = (const El *)h->pop[h->cur];
-  hipLaunchKernelGGL(k_moments<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
+  hipLaunchKernelGGL((k_moments<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
                      S, S + (size_t)Q * h->g.qs, n, e, beta, sums ? h->d_part : nullptr);
   if (sums)
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(BLOCK), 0, h->stream, h->d_part, h->p.batch,
@@ -226,22 +233,22 @@ rlb_status launch_moments(rlb_solver *h, double *n, double *e, double *beta, boo
   return RLB_OK;
 }
 
-template <int ST>
+template <int ST, class TC>
 rlb_status launch_fields_g(rlb_solver *h, const void *Sg, double *e, double *beta) {
-  using El = typename Codec<ST>::elem;
-  hipLaunchKernelGGL(k_moments<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
+  using El = typename Codec<ST, TC>::elem;
+  hipLaunchKernelGGL((k_moments<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
                      (const El *)nullptr, (const El *)Sg, (double *)nullptr, e, beta,
                      (double *)nullptr);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
 
-template <int ST>
+template <int ST, class TC>
 rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_next, void *lam_out,
                           double *dtau, double *dbeta_in, double *de_in) {
-  using El = typename Codec<ST>::elem;
-  using Lm = typename Codec<ST>::lam;
-  hipLaunchKernelGGL(k_adjoint<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
+  using El = typename Codec<ST, TC>::elem;
+  using Lm = typename Codec<ST, TC>::lam;
+  hipLaunchKernelGGL((k_adjoint<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
                      (const El *)S, (const Lm *)lam_next, (Lm *)lam_out, (Lm *)h->d_scratch,
                      h->d_part, h->in);
   if (h->faces.count > 0) {
@@ -257,23 +264,23 @@ rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_next, vo
   return RLB_OK;
 }
 
-template <int ST>
+template <int ST, class TC>
 rlb_status launch_moments_adjoint(rlb_solver *h, const void *S, const double *dLde,
                                   const double *dLdb, void *lam) {
-  using El = typename Codec<ST>::elem;
-  using Lm = typename Codec<ST>::lam;
-  hipLaunchKernelGGL(k_moments_adjoint<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream,
+  using El = typename Codec<ST, TC>::elem;
+  using Lm = typename Codec<ST, TC>::lam;
+  hipLaunchKernelGGL((k_moments_adjoint<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream,
                      h->g, h->ph, (const El *)S, dLde, dLdb, (Lm *)lam);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
 
-template <int ST>
+template <int ST, class TC>
 rlb_status launch_init_adjoint(rlb_solver *h, const double *e0, const double *beta0,
                                const void *lam0, double *de0, double *db0, double *dbeta_in,
                                double *de_in) {
-  using Lm = typename Codec<ST>::lam;
-  hipLaunchKernelGGL(k_init_adjoint<ST>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+  using Lm = typename Codec<ST, TC>::lam;
+  hipLaunchKernelGGL((k_init_adjoint<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
                      h->ph, e0, beta0, (const Lm *)lam0, de0, db0, h->d_part, h->in);
   if (dbeta_in || de_in)
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(BLOCK), 0, h->stream, h->d_part, h->p.batch,
@@ -282,16 +289,32 @@ rlb_status launch_init_adjoint(rlb_solver *h, const double *e0, const double *be
   return RLB_OK;
 }
 
-// Storage dispatch: DISPATCH(fn, args...) calls fn<ST>(args...).
-#define RLB_DISPATCH(st, fn, ...)                                       \
-  switch (st) {                                                         \
-    case ST_F64: return fn<ST_F64>(__VA_ARGS__);                        \
-    case ST_F32: return fn<ST_F32>(__VA_ARGS__);                        \
-    case ST_F32DEV: return fn<ST_F32DEV>(__VA_ARGS__);                  \
-    case ST_F16DEV: return fn<ST_F16DEV>(__VA_ARGS__);                  \
-    case ST_BF16DEV: return fn<ST_BF16DEV>(__VA_ARGS__);                \
-  }                                                                     \
-  return fail(RLB_EINVAL, "unknown storage")
+// Storage x compute-type dispatch: RLB_DISPATCH(h, fn, args...) calls
+// fn<ST, TC>(args...) for the solver's storage and collision type.
+#define RLB_DISPATCH(h, fn, ...)                                                   \
+  do {                                                                             \
+    const bool c64_ = (h)->cp == RLB_COLLIDE_F64;                                  \
+    switch ((h)->st) {                                                             \
+      case ST_F64: return fn<ST_F64, double>(__VA_ARGS__);                         \
+      case ST_F32:                                                                 \
+        return c64_ ? fn<ST_F32, double>(__VA_ARGS__) : fn<ST_F32, float>(__VA_ARGS__); \
+      case ST_F32DEV:                                                              \
+        return c64_ ? fn<ST_F32DEV, double>(__VA_ARGS__)                           \
+                    : fn<ST_F32DEV, float>(__VA_ARGS__);                           \
+      case ST_F16DEV: return fn<ST_F16DEV, float>(__VA_ARGS__);                    \
+      case ST_BF16DEV: return fn<ST_BF16DEV, float>(__VA_ARGS__);                  \
+    }                                                                              \
+    return fail(RLB_EINVAL, "unknown storage");                                    \
+  } while (0)
+
+// Resolved collision type: AUTO is FP64 for the 8- and 4-byte storages (the
+// FP32 rounding of the collision itself would dominate their error) and FP32
+// for the 2-byte storages (their storage rounding dominates).
+int resolve_collide(const rlb_params *p) {
+  if (p->collide != RLB_COLLIDE_AUTO) return p->collide;
+  return (p->storage == RLB_F16DEV || p->storage == RLB_BF16DEV) ? RLB_COLLIDE_F32
+                                                                 : RLB_COLLIDE_F64;
+}
 
 void free_solver(rlb_solver *h) {
   if (!h) return;
@@ -344,6 +367,7 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
   std::memset(h, 0, sizeof(*h));
   h->p = *p;
   h->st = p->storage;
+  h->cp = resolve_collide(p);
   h->elem = elem_size(p->storage);
   h->lam_elem = p->storage == RLB_F64 ? 8 : 4;
   h->pop[0] = pop_a;
@@ -395,7 +419,7 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
     ph.cls = h->d_cls;
   }
   ph.omega = h->d_omega;
-  auto launch = [&]() -> rlb_status { RLB_DISPATCH(h->st, launch_init, h, n0, e0, beta0); };
+  auto launch = [&]() -> rlb_status { RLB_DISPATCH(h, launch_init, h, n0, e0, beta0); };
   s = launch();
   if (s == RLB_OK && (e = hipStreamSynchronize(h->stream)) != hipSuccess)
     s = fail(RLB_EDEVICE, std::string("rlb_init: ") + hipGetErrorString(e));
@@ -410,13 +434,13 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
 rlb_status rlb_step(rlb_solver *h, int32_t nsteps) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   if (nsteps < 0) return fail(RLB_EINVAL, "nsteps must be >= 0");
-  RLB_DISPATCH(h->st, launch_steps, h, nsteps);
+  RLB_DISPATCH(h, launch_steps, h, nsteps);
 }
 
 rlb_status rlb_step_g(rlb_solver *h, const void *g_src, void *g_dst) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   if (!g_src || !g_dst || g_src == g_dst) return fail(RLB_EINVAL, "g_src/g_dst invalid");
-  RLB_DISPATCH(h->st, launch_step_g, h, g_src, g_dst);
+  RLB_DISPATCH(h, launch_step_g, h, g_src, g_dst);
 }
 
 rlb_status rlb_current(rlb_solver *h, void **state) {
@@ -429,7 +453,7 @@ rlb_status rlb_current(rlb_solver *h, void **state) {
 rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double *sums) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   auto launch = [&]() -> rlb_status {
-    RLB_DISPATCH(h->st, launch_moments, h, n, e, beta, sums != nullptr);
+    RLB_DISPATCH(h, launch_moments, h, n, e, beta, sums != nullptr);
   };
   rlb_status s = launch();
   if (s != RLB_OK || !sums) return s;
@@ -442,7 +466,7 @@ rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double
 rlb_status rlb_fields_g(rlb_solver *h, const void *g_state, double *e, double *beta) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   if (!g_state || (!e && !beta)) return fail(RLB_EINVAL, "g_state or outputs invalid");
-  RLB_DISPATCH(h->st, launch_fields_g, h, g_state, e, beta);
+  RLB_DISPATCH(h, launch_fields_g, h, g_state, e, beta);
 }
 
 rlb_status rlb_counters(rlb_solver *h, int64_t counts[2]) {
@@ -469,7 +493,7 @@ rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *la
     return fail(RLB_EINVAL, "adjoint buffers invalid");
   if (h->faces.count > 0 && !h->d_scratch)
     RLB_HIP(hipMalloc(&h->d_scratch, (size_t)Q * h->g.qs * h->lam_elem));
-  RLB_DISPATCH(h->st, launch_adjoint, h, g_state_t, lam_next, lam_out, dL_dtau, dL_dbeta_in,
+  RLB_DISPATCH(h, launch_adjoint, h, g_state_t, lam_next, lam_out, dL_dtau, dL_dbeta_in,
                dL_de_in);
 }
 
@@ -478,7 +502,7 @@ rlb_status rlb_moments_adjoint(rlb_solver *h, const void *g_state_T, const doubl
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   if (!g_state_T || !dL_de || !dL_dbeta || !lam_T)
     return fail(RLB_EINVAL, "a required pointer is NULL");
-  RLB_DISPATCH(h->st, launch_moments_adjoint, h, g_state_T, dL_de, dL_dbeta, lam_T);
+  RLB_DISPATCH(h, launch_moments_adjoint, h, g_state_T, dL_de, dL_dbeta, lam_T);
 }
 
 rlb_status rlb_init_adjoint(rlb_solver *h, const double *e0, const double *beta0,
@@ -487,7 +511,7 @@ rlb_status rlb_init_adjoint(rlb_solver *h, const double *e0, const double *beta0
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   if (!e0 || !beta0 || !lam_0 || !dL_de0 || !dL_dbeta0)
     return fail(RLB_EINVAL, "a required pointer is NULL");
-  RLB_DISPATCH(h->st, launch_init_adjoint, h, e0, beta0, lam_0, dL_de0, dL_dbeta0, dL_dbeta_in,
+  RLB_DISPATCH(h, launch_init_adjoint, h, e0, beta0, lam_0, dL_de0, dL_dbeta0, dL_dbeta_in,
                dL_de_in);
 }
 

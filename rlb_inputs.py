@@ -29,8 +29,9 @@ import numpy as np
 
 PERIODIC, OUTFLOW, INFLOW = 0, 1, 2
 
-# Storage codes (same numbering as the C header's enum).
+# Storage and collision-type codes (same numbering as the C header's enums).
 F64, F32, F32DEV, F16DEV, BF16DEV = 0, 1, 2, 3, 4
+COLLIDE_AUTO, COLLIDE_F32, COLLIDE_F64 = 0, 1, 2
 STORAGE_NAMES = {F64: "f64", F32: "f32", F32DEV: "f32dev", F16DEV: "f16dev", BF16DEV: "bf16dev"}
 
 
@@ -49,6 +50,7 @@ class Setup:
     tau: np.ndarray = field(default_factory=lambda: np.array([0.6]))
     steps: int = 100
     storage: int = F64
+    collide: int = COLLIDE_AUTO
     n_ref: float = 1.0
     e_ref: float = 1.0
     n0: Optional[np.ndarray] = None  # [cells]
@@ -159,16 +161,31 @@ def periodic_box(n=256, steps=1000, storage=F64, beta_max=0.2, de=0.1, tau=0.6, 
 
 
 def tube_batch(batch=64, nz=2048, steps=2000, storage=F32, seed=2, tau_range=(0.51, 1.0),
-               ratio_range=(4.0, 32.0)):
-    """Batch of independent shock tubes; returns (setup, tau[b], ratio[b])."""
+               ratio_range=(4.0, 32.0), reject=None):
+    """Batch of independent shock tubes with tau_b ~ U[tau_range] and
+    e_L/e_R = r_b ~ U[ratio_range] (e_L = 1).
+
+    ``reject`` (optional) is a callable taking (tau, ratio) arrays and returning
+    the indices of instances to draw again (for instance those a screening run
+    found unphysical); they are redrawn from the same seeded stream, in index
+    order, until none is rejected.  Returns (setup, tau, ratio, n_redrawn)."""
     rng = np.random.default_rng(seed)
     tau = rng.uniform(*tau_range, size=batch)
     ratio = rng.uniform(*ratio_range, size=batch)
+    redrawn = 0
+    while reject is not None:
+        bad = sorted(int(i) for i in reject(tau.copy(), ratio.copy()))
+        if not bad:
+            break
+        for i in bad:
+            tau[i] = rng.uniform(*tau_range)
+            ratio[i] = rng.uniform(*ratio_range)
+            redrawn += 1
     s = shock_tube(nz=nz, e_L=np.ones(batch), e_R=1.0 / ratio, tau=0.6, steps=steps,
                    batch=batch, storage=storage)
     s.name = "tube_batch"
-    s.tau = tau
-    return s, tau, ratio
+    s.tau = tau.copy()
+    return s, tau, ratio, redrawn
 
 
 def sphere_large(steps=4000, storage=F32) -> Setup:

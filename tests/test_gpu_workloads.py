@@ -1,0 +1,216 @@
+"""The full-size workloads: mixed-precision storage on the 256^3 periodic box,
+the 64-tube adjoint batch and the large sphere adjoint.
+
+Mixed precision is measured against the FP64 run of the same GPU path (itself
+pinned to the oracle at 1e-12 per step, sampled at this size) and, at a size the
+oracle runs in seconds, against the oracle directly.  Gradients are checked
+against central differences of FP64 forward runs and, for tubes, against
+complex-step derivatives of the independent lumped 1-D oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rlb_inputs as ri
+from helpers import problem
+from oracle import d1q3
+
+pytestmark = pytest.mark.gpu
+
+# Tolerances of the 2-byte storages after 1000 steps: storage rounding with unit
+# roundoff u on deviations of up to ~0.2 of the field, accumulated as a random
+# walk over 1000 steps (~sqrt(1000) ~ 32), gives ~6u; u = 2^-11 (FP16), 2^-8 (BF16).
+TOL_16 = {ri.F16DEV: 6 * 2.0 ** -11, ri.BF16DEV: 6 * 2.0 ** -8}
+
+
+def fields(s, steps):
+    from paper_0912_2913_amd.solver import Solver
+
+    sv = Solver(s)
+    sv.step(steps)
+    _, e, b = sv.moments()
+    counts = sv.counters()
+    sv.close()
+    del sv
+    torch.cuda.empty_cache()
+    return e, b, counts
+
+
+def rel(a, b):
+    return float((a - b).abs().max() / b.abs().max())
+
+
+def test_mixed_precision_box_256_1000_steps():
+    ref = ri.periodic_box()
+    e64, b64, c = fields(ref, 1000)
+    assert c == (0, 0)
+    errs = {}
+    for st, collide in [(ri.F32, ri.COLLIDE_AUTO), (ri.F32DEV, ri.COLLIDE_AUTO),
+                        (ri.F32, ri.COLLIDE_F32), (ri.F32DEV, ri.COLLIDE_F32),
+                        (ri.F16DEV, ri.COLLIDE_AUTO), (ri.BF16DEV, ri.COLLIDE_AUTO)]:
+        s = ri.periodic_box(storage=st)
+        s.collide = collide
+        e, b, c = fields(s, 1000)
+        assert c[0] == 0
+        errs[(ri.STORAGE_NAMES[st], collide)] = (rel(e, e64), rel(b, b64))
+    print(errs)
+    # FP32 storage (FP64 collision, the default): the 1e-5 target with margin
+    for name in ("f32", "f32dev"):
+        ee, eb = errs[(name, ri.COLLIDE_AUTO)]
+        assert ee <= 1e-6 and eb <= 1e-6, (name, ee, eb)
+    # FP32 storage with FP32 collision: per-step FP32 rounding of the collision
+    # accumulates to ~2e-5 in the max norm over 16.7M cells
+    for name in ("f32", "f32dev"):
+        ee, eb = errs[(name, ri.COLLIDE_F32)]
+        assert ee <= 1e-4 and eb <= 1e-4, (name, ee, eb)
+    for st in (ri.F16DEV, ri.BF16DEV):
+        ee, eb = errs[(ri.STORAGE_NAMES[st], ri.COLLIDE_AUTO)]
+        assert ee <= TOL_16[st] and eb <= TOL_16[st], (st, ee, eb)
+
+
+@pytest.mark.parametrize("st", [ri.F32, ri.F32DEV, ri.F16DEV, ri.BF16DEV])
+def test_mixed_precision_small_box_against_oracle(st):
+    """32^3 periodic box, 200 steps, each storage against the FP64 oracle."""
+    s = ri.periodic_box(n=32, storage=st, beta_max=0.2)
+    p = problem(s)
+    S = oracle.init(p, s.n0, s.e0, s.beta0)
+    oracle.run(p, S, 200)
+    _, e, b, _ = oracle.moments(p, S)
+    ge, gb, _ = fields(s, 200)
+    ee = float(np.abs(ge.cpu().numpy() - e).max() / np.abs(e).max())
+    eb = float(np.abs(gb.cpu().numpy() - b).max() / np.abs(b).max())
+    tol = 1e-6 if st in (ri.F32, ri.F32DEV) else TOL_16[st]
+    assert ee <= tol and eb <= tol, (ee, eb)
+
+
+# ----------------------------------------------------------------------------- tubes
+def _screen_tubes(storages=(ri.F64, ri.F32)):
+    """reject() for rlb_inputs.tube_batch: instances whose nominal run, or the run
+    at (1.02 tau, 1.05 ratio) that makes the target, goes unphysical in any of the
+    given storages within 2000 steps (NaN persists once it appears)."""
+
+    def reject(tau, ratio):
+        bad = set()
+        for t_, r_ in ((tau, ratio), (1.02 * tau, 1.05 * ratio)):
+            for st in storages:
+                s = ri.shock_tube(nz=2048, e_L=np.ones(tau.size), e_R=1.0 / r_, batch=tau.size,
+                                  storage=st)
+                s.tau = t_
+                e, _, _ = fields(s, 2000)
+                e = e.view(tau.size, -1)
+                bad |= set(torch.nonzero(~torch.isfinite(e).all(1) | (e <= 0).any(1))
+                           .flatten().tolist())
+        return bad
+
+    return reject
+
+
+def _tube_loss_fp64(tau, ratio, target, steps=2000, e0=None):
+    """Per-instance loss sum_z (e_T - target)^2 of FP64 GPU forward runs."""
+    from paper_0912_2913_amd.autograd import rlb_run
+
+    s = ri.shock_tube(nz=2048, e_L=np.ones(tau.size), e_R=1.0 / ratio, batch=tau.size)
+    s.tau = np.asarray(tau, dtype=np.float64)
+    if e0 is not None:
+        s.e0 = e0
+    with torch.no_grad():
+        e, _ = rlb_run(s, steps, checkpoint="sqrt")
+    return ((e.view(tau.size, -1) - target) ** 2).sum(1).cpu().numpy()
+
+
+def test_tube_batch_adjoint_sqrtT():
+    """64 tubes x 2048 cells, FP32 storage, 2000 steps with sqrt(T) checkpointing:
+    gradients of sum_b sum_z (e_T - target)^2 with respect to tau_b and e0 against
+    central FD of FP64 runs (<= 1e-4) and complex-step of the lumped 1-D oracle."""
+    from paper_0912_2913_amd.autograd import rlb_run
+
+    s, tau, ratio, redrawn = ri.tube_batch(reject=_screen_tubes())
+    print("instances redrawn by the screen:", redrawn)
+    dev = "cuda:0"
+    # target: FP64 final e of each instance at (1.02 tau, 1.05 ratio)
+    st = ri.shock_tube(nz=2048, e_L=np.ones(64), e_R=1.0 / (1.05 * ratio), batch=64)
+    st.tau = 1.02 * tau
+    with torch.no_grad():
+        target, _ = rlb_run(st, 2000)
+    target = target.view(64, -1)
+    grads = {}
+    for storage in (ri.F32, ri.F64):
+        s2 = s.with_(storage=storage)
+        tau_t = torch.tensor(tau, device=dev, requires_grad=True)
+        e0_t = torch.tensor(s2.e0, device=dev, requires_grad=True)
+        e, _ = rlb_run(s2, 2000, tau=tau_t, e0=e0_t, checkpoint="sqrt")
+        L = ((e.view(64, -1) - target) ** 2).sum()
+        L.backward()
+        grads[storage] = (tau_t.grad.cpu().numpy(), e0_t.grad.cpu().numpy())
+    # FD in FP64 over tau: instances are independent, so one +-h pair gives all 64
+    h = 1e-6
+    Lp = _tube_loss_fp64(tau + h, ratio, target)
+    Lm = _tube_loss_fp64(tau - h, ratio, target)
+    fd_tau = (Lp - Lm) / (2 * h)
+    for storage, tol in ((ri.F64, 1e-7), (ri.F32, 1e-4)):
+        gt = grads[storage][0]
+        err = np.abs(gt - fd_tau).max() / np.abs(fd_tau).max()
+        assert err <= tol, (storage, err)
+    # directional derivative in e0 along a smooth direction per instance
+    z = np.arange(2048)
+    v = np.concatenate([np.sin(2 * np.pi * (k + 1) * z / 2048) * 1e-2 for k in range(64)])
+    Lp = _tube_loss_fp64(tau, ratio, target, e0=s.e0 + h * v).sum()
+    Lm = _tube_loss_fp64(tau, ratio, target, e0=s.e0 - h * v).sum()
+    fd_v = (Lp - Lm) / (2 * h)
+    for storage, tol in ((ri.F64, 1e-6), (ri.F32, 1e-4)):
+        gv = float(grads[storage][1] @ v)
+        assert gv == pytest.approx(fd_v, rel=tol), (storage, gv, fd_v)
+    # complex-step reference on two instances from the lumped 1-D oracle (FP64)
+    tg = target.cpu().numpy()
+    for b in (0, 37):
+        n0 = s.n0.reshape(64, -1)[b]
+        e0 = s.e0.reshape(64, -1)[b]
+        hh = 1e-30
+        _, ec, _ = d1q3.run(n0, e0, np.zeros(2048), tau[b] + 1j * hh, 1.0, 2000)
+        dL = float((2 * (ec.real - tg[b]) * ec.imag / hh).sum())
+        assert grads[ri.F64][0][b] == pytest.approx(dL, rel=1e-8)
+        assert grads[ri.F32][0][b] == pytest.approx(dL, rel=1e-4)
+
+
+# ----------------------------------------------------------------------------- large sphere
+LARGE_STEPS = 110  # the large sphere set-up stays physical up to ~step 120 at c_l = 1
+
+
+@pytest.mark.parametrize("storage,tol", [(ri.F32, 1e-4), (ri.BF16DEV, 5e-2)])
+def test_large_sphere_adjoint_surface_pressure(storage, tol):
+    """384 x 192 x 192 with a radius-24 sphere: gradient of the integrated
+    pressure P = e/3 on the fluid cells touching the sphere with respect to the
+    inflow velocity, tau and the initial e field, under sqrt(T) checkpointing,
+    against central FD of FP64 runs."""
+    from paper_0912_2913_amd.autograd import rlb_run, surface_mask
+
+    dev = "cuda:0"
+    s = ri.sphere_large(steps=LARGE_STEPS, storage=storage)
+    mask = torch.as_tensor(surface_mask(s), device=dev)
+    bin_t = torch.tensor(s.inflow[2:5], dtype=torch.float64, device=dev, requires_grad=True)
+    tau_t = torch.tensor(s.tau, device=dev, requires_grad=True)
+    e0_t = torch.tensor(s.e0, device=dev, requires_grad=True)
+    e, _ = rlb_run(s, LARGE_STEPS, tau=tau_t, beta_in=bin_t, e0=e0_t)
+    L = (e[mask] / 3.0).sum()
+    L.backward()
+    assert torch.isfinite(L)
+
+    def loss64(**kw):
+        s64 = s.with_(storage=ri.F64, **kw)
+        with torch.no_grad():
+            e64, _ = rlb_run(s64, LARGE_STEPS)
+        return float((e64[mask] / 3.0).sum())
+
+    h = 1e-6
+    bi = np.array(s.inflow)
+    fd_b = (loss64(inflow=tuple(bi + [0, 0, h, 0, 0])) - loss64(inflow=tuple(bi - [0, 0, h, 0, 0]))) / (2 * h)
+    assert float(bin_t.grad[0]) == pytest.approx(fd_b, rel=tol)
+    fd_t = (loss64(tau=s.tau + h) - loss64(tau=s.tau - h)) / (2 * h)
+    assert float(tau_t.grad[0]) == pytest.approx(fd_t, rel=tol)
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(s.cells) * 1e-2 * (s.solid == 0)
+    fd_v = (loss64(e0=s.e0 + h * v) - loss64(e0=s.e0 - h * v)) / (2 * h)
+    assert float(e0_t.grad.cpu().numpy() @ v) == pytest.approx(fd_v, rel=tol)
