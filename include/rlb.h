@@ -32,8 +32,7 @@
  *    clamped into the domain); INFLOW holds the face plane at the equilibrium
  *    of (inflow_n, inflow_e, inflow_beta).  Solid cells reflect by half-way
  *    bounce-back and are never updated.
- *  - Adjoint buffers ("lambda"): [19][q_stride], double for RLB_F64 storage,
- *    float for every other storage.
+ *  - Adjoint buffers ("lambda"): [19][q_stride] double, for every storage.
  *  - Device pointers address memory on the solver's device; every call that
  *    launches work is asynchronous on the stream given to rlb_init unless its
  *    comment says it synchronises.  Nothing throws across the ABI.

@@ -12,6 +12,11 @@
 
 namespace rlb {
 
+// Adjoint (lambda) buffers are FP64 for every storage: lambda carries a large
+// component along the collision invariants that cancels in every contraction
+// with (pre - eq); stored in FP32 its rounding swamps the small remainder.
+using LamT = double;
+
 enum { ST_F64 = 0, ST_F32 = 1, ST_F32DEV = 2, ST_F16DEV = 3, ST_BF16DEV = 4 };
 
 // bfloat16 = the upper 16 bits of an IEEE binary32.  Encoding rounds to
@@ -29,7 +34,6 @@ struct Format;
 template <>
 struct Format<ST_F64> {
   using elem = double;
-  using lam = double;  // adjoint buffers
   static constexpr bool dev = false;
   template <class T>
   __device__ static T dec(elem v) { return (T)v; }
@@ -40,7 +44,6 @@ struct Format<ST_F64> {
 template <>
 struct Format<ST_F32> {
   using elem = float;
-  using lam = float;
   static constexpr bool dev = false;
   template <class T>
   __device__ static T dec(elem v) { return (T)v; }
@@ -57,7 +60,6 @@ struct Format<ST_F32DEV> : Format<ST_F32> {
 template <>
 struct Format<ST_F16DEV> {
   using elem = _Float16;
-  using lam = float;
   static constexpr bool dev = true;
   template <class T>
   __device__ static T dec(elem v) { return (T)(float)v; }
@@ -69,7 +71,6 @@ struct Format<ST_F16DEV> {
 template <>
 struct Format<ST_BF16DEV> {
   using elem = uint16_t;
-  using lam = float;
   static constexpr bool dev = true;
   template <class T>
   __device__ static T dec(elem v) { return (T)__uint_as_float((uint32_t)v << 16); }
@@ -82,7 +83,7 @@ struct Codec {
   using F = Format<ST>;
   using elem = typename F::elem;
   using calc = TC;
-  using lam = typename F::lam;
+  using lam = LamT;
   static constexpr bool dev = F::dev;
   __device__ static calc dec(elem v) { return F::template dec<calc>(v); }
   __device__ static elem enc(calc v) { return F::enc(v); }

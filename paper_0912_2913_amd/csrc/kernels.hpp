@@ -211,8 +211,13 @@ __device__ __forceinline__ Pull pull_general(const Geom &g, const Phys &ph, cons
 // perturbations (1-D shock tubes at e_L/e_R = 16 amplify them ~20x per 10
 // steps), so that residual alone would seed a transverse blow-up of an
 // otherwise one-dimensional flow.
+//
+// Contraction is off here: if v_i is a product (as in the reverse step),
+// fusing it into the difference would compute exact(v_i) - rounded(v_j) and
+// leave that rounding error as a residual, the same seed as above.
 template <class T>
 __device__ __forceinline__ void mirror_sums(const T (&v)[Q], T &mx, T &my, T &mz) {
+#pragma clang fp contract(off)
   mx = ((v[1] - v[2]) + (v[7] - v[10])) + ((v[9] - v[8]) + (v[11] - v[14])) + (v[13] - v[12]);
   my = ((v[3] - v[4]) + (v[7] - v[9])) + ((v[10] - v[8]) + (v[15] - v[18])) + (v[17] - v[16]);
   mz = ((v[5] - v[6]) + (v[11] - v[13])) + ((v[14] - v[12]) + (v[15] - v[17])) + (v[18] - v[16]);
@@ -736,7 +741,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
     typename Codec<ST, TC>::lam *__restrict__ lam_out, typename Codec<ST, TC>::lam *__restrict__ scratch,
     double *__restrict__ part, const InflowState in) {
   using Cd = Codec<ST, TC>;
-  using T = typename Cd::calc;
+  using T = double;  // reverse-mode arithmetic is FP64 for every storage
   using Lm = typename Cd::lam;
   const Cell c = decode_cell(g);
   const size_t qs = (size_t)g.qs;
@@ -766,12 +771,12 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
       const FaceCorr fc = face_corr(g, c);
       if (fast) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) pre[q] = Cd::dec(S[q * qs + src_fast(g, c, fc, q)]);
+        for (int q = 0; q < Q; ++q) pre[q] = (T)Cd::dec(S[q * qs + src_fast(g, c, fc, q)]);
       } else {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
           const Pull p = pull_general(g, ph, c, q);
-          pre[q] = Cd::dec(S[p.q * qs + p.idx]);
+          pre[q] = (T)Cd::dec(S[p.q * qs + p.idx]);
         }
       }
 #pragma unroll
@@ -944,7 +949,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_adjoint(
     const typename Codec<ST, TC>::lam *__restrict__ lam0, double *__restrict__ de0,
     double *__restrict__ db0, double *__restrict__ part, const InflowState in) {
   using Cd = Codec<ST, TC>;
-  using T = typename Cd::calc;
+  using T = double;  // reverse-mode arithmetic is FP64 for every storage
   const Cell c = decode_cell(g);
   const size_t qs = (size_t)g.qs;
   const size_t cells = (size_t)g.batch * g.per;

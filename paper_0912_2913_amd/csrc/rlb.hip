@@ -369,7 +369,7 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
   h->st = p->storage;
   h->cp = resolve_collide(p);
   h->elem = elem_size(p->storage);
-  h->lam_elem = p->storage == RLB_F64 ? 8 : 4;
+  h->lam_elem = sizeof(LamT);
   h->pop[0] = pop_a;
   h->pop[1] = pop_b;
   h->cur = 0;

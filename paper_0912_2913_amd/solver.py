@@ -70,7 +70,7 @@ class Solver:
         self.cells = s.batch * s.nz * s.ny * s.nx
         self.storage = int(s.storage)
         self.dtype = STORAGE_DTYPE[self.storage]
-        self.lam_dtype = torch.float64 if self.storage == _lib.F64 else torch.float32
+        self.lam_dtype = torch.float64  # adjoint buffers are FP64 for every storage
         self.q_stride, self.state_bytes = buffer_layout(self.params)
         with torch.cuda.stream(self.stream):
             self.pop = [torch.empty((2, Q, self.q_stride), dtype=self.dtype, device=self.device)
