@@ -583,16 +583,23 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const Geom g, const Phys ph,
 //   dtau != null: dtau[b] += sum of component 0;
 //   dinflow != null: dinflow[0..3] += sum over all blocks of components 1..4
 //   (order: e_in, beta_in x, y, z -> dL_de_in, dL_dbeta_in[3]).
+//   part2/start2 (optional): a second set of per-workgroup partials whose
+//   instance b owns workgroups [start2[b], start2[b+1]), added after part's.
 __global__ __launch_bounds__(BLOCK) void k_finish(const double *__restrict__ part, int batch,
                                                   int nblk_per, double *__restrict__ res,
                                                   double *__restrict__ dtau,
                                                   double *__restrict__ de_in,
-                                                  double *__restrict__ dbeta_in) {
+                                                  double *__restrict__ dbeta_in,
+                                                  const double *__restrict__ part2,
+                                                  const int *__restrict__ start2) {
   double total[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = 0; b < batch; ++b) {
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int j = (int)threadIdx.x; j < nblk_per; j += BLOCK)
       for (int k = 0; k < 5; ++k) v[k] += part[((size_t)b * nblk_per + j) * 5 + k];
+    if (part2)
+      for (int j = start2[b] + (int)threadIdx.x; j < start2[b + 1]; j += BLOCK)
+        for (int k = 0; k < 5; ++k) v[k] += part2[(size_t)j * 5 + k];
     double out[5];
     block_sum<5>(v, out);
     if (threadIdx.x == 0) {
@@ -730,101 +737,177 @@ __device__ __forceinline__ bool covered(const Geom &g, const Phys &ph, const Cel
   return false;
 }
 
-// One reverse step of the g population (see rlb_adjoint_step).  Writes
-// lambda_t for every direction of every cell except the clamped-pull
-// contributions, which go to `scratch` (indexed by the reading cell) and are
-// added by k_adjoint_faces.  part[L][5] = (dtau, de_in, dbeta_in[3]) partials.
+// Which reverse-step kernel handles a cell: the streaming kernel takes cells
+// whose 19 sources and 19 targets are all plain (possibly wrapped) neighbours;
+// every other cell (solid, inflow, next to a solid, on an outflow face or next
+// to an inflow plane) goes to the general kernel, through a precomputed list.
+__device__ __forceinline__ bool adjoint_plain(const Geom &g, const Phys &ph, const Cell &c) {
+  const uint8_t cls = ph.cls ? ph.cls[c.idx] : (uint8_t)0;
+  return !(cls & (CLS_SOLID | CLS_NEAR)) && !is_inflow(g, c.x, c.y, c.z) &&
+         in_fast(c, g.alo, g.ahi);
+}
+
+// Cell of a linear index (general kernel).
+__device__ __forceinline__ Cell cell_at(const Geom &g, long long idx) {
+  Cell c;
+  c.idx = idx;
+  c.b = (int)(idx / g.per);
+  c.local = (int)(idx - (long long)c.b * g.per);
+  c.active = true;
+  const uint32_t t = fdiv(g.div_x, (uint32_t)c.local);
+  c.x = c.local - (int)t * g.n[0];
+  const uint32_t z = fdiv(g.div_y, t);
+  c.y = (int)t - (int)z * g.n[1];
+  c.z = (int)z;
+  c.L = 0;
+  return c;
+}
+
+// Local reverse update of one updated cell: from the pulled populations pre
+// and lambda_{t+1}(x), the contributions mu_q to lambda_t (one per pulled
+// population) and lambda . d post / d tau.
+struct LocalAdjoint {
+  double om1, aE, ax, ay, az, dtau;
+};
+
+template <class T>
+__device__ __forceinline__ LocalAdjoint adjoint_local(const Phys &ph, double om, const T (&pre)[Q],
+                                                      const T (&lam)[Q]) {
+  T sE = (T)0, sx, sy, sz;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) sE += pre[q];
+  mirror_sums(pre, sx, sy, sz);
+  const Inv iv = invert(ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
+                        ph.c * (double)sz);
+  const EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
+  const LamEq L = lam_eq(lam_sums(lam, k), ph, iv.W, iv.bx, iv.by, iv.bz);
+  const GradEM gm = chain_moments(iv, L.Le, L.LW, L.Lbx, L.Lby, L.Lbz);
+  LocalAdjoint r;
+  r.om1 = 1.0 - om;
+  r.aE = om * gm.gE;
+  r.ax = om * ph.c * gm.gx;
+  r.ay = om * ph.c * gm.gy;
+  r.az = om * ph.c * gm.gz;
+  T dt = (T)0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) dt += lam[q] * (pre[q] - geq_dev(k, q));
+  r.dtau = om * om * (double)dt;
+  return r;
+}
+
+// mu_q = (1 - omega) lambda_q + omega (dL/dE + c_l e_q . dL/dM)
+__device__ __forceinline__ double adjoint_mu(const LocalAdjoint &a, double lam, int q) {
+  double mu = a.om1 * lam + a.aE;
+  if (EX[q] == 1) mu += a.ax;
+  if (EX[q] == -1) mu -= a.ax;
+  if (EY[q] == 1) mu += a.ay;
+  if (EY[q] == -1) mu -= a.ay;
+  if (EZ[q] == 1) mu += a.az;
+  if (EZ[q] == -1) mu -= a.az;
+  return mu;
+}
+
+// One reverse step of the g population (see rlb_adjoint_step), streaming part:
+// cells for which adjoint_plain() holds.  Each pulls pre from S_t, reads
+// lambda_{t+1}(x) and writes mu_q to lambda_t at the source of its pull q;
+// those targets cover every entry of lambda_t that no general cell writes.
+// part[L][5] = (dtau, 0, 0, 0, 0) partials of this workgroup.
 template <int ST, class TC>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(
     const Geom g, const Phys ph, const typename Codec<ST, TC>::elem *__restrict__ S,
-    const typename Codec<ST, TC>::lam *__restrict__ lam_next,
-    typename Codec<ST, TC>::lam *__restrict__ lam_out, typename Codec<ST, TC>::lam *__restrict__ scratch,
-    double *__restrict__ part, const InflowState in) {
+    const LamT *__restrict__ lam_next, LamT *__restrict__ lam_out, double *__restrict__ part) {
   using Cd = Codec<ST, TC>;
-  using T = double;  // reverse-mode arithmetic is FP64 for every storage
-  using Lm = typename Cd::lam;
   const Cell c = decode_cell(g);
   const size_t qs = (size_t)g.qs;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (c.active) {
-    const uint8_t cls = ph.cls ? ph.cls[c.idx] : (uint8_t)0;
-    const bool solid = cls & CLS_SOLID;
-    const bool inflow = !solid && is_inflow(g, c.x, c.y, c.z);
-    const bool fast = !solid && !inflow && !(cls & CLS_NEAR) && in_fast(c, g.alo, g.ahi);
-    if (!fast) {
-      for (int p = 0; p < Q; ++p)
-        if (solid || !covered(g, ph, c, p, inflow)) lam_out[p * qs + c.idx] = (Lm)0;
-    }
-    if (inflow) {
-      T lam[Q];
+  if (c.active && adjoint_plain(g, ph, c)) {
+    double pre[Q], lam[Q];
+    const FaceCorr fc = face_corr(g, c);
 #pragma unroll
-      for (int q = 0; q < Q; ++q) lam[q] = (T)lam_next[q * qs + c.idx];
-      const double g2 = 1.0 / (1.0 - (in.bx * in.bx + in.by * in.by + in.bz * in.bz));
-      const double W = (4.0 / 3.0) * in.e * g2;
-      const EqCoef<T> k = eq_coef<T>(ph, 0.0, in.e, W, in.bx, in.by, in.bz);
-      const LamEq L = lam_eq(lam_sums(lam, k), ph, W, in.bx, in.by, in.bz);
-      double gr[4];
-      eq_param_grad(L, in.e, in.bx, in.by, in.bz, gr);
-      for (int k2 = 0; k2 < 4; ++k2) acc[1 + k2] = gr[k2];
-    } else if (!solid) {
-      T pre[Q], lam[Q];
-      const FaceCorr fc = face_corr(g, c);
-      if (fast) {
+    for (int q = 0; q < Q; ++q) pre[q] = (double)Cd::dec(S[q * qs + src_fast(g, c, fc, q)]);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) pre[q] = (T)Cd::dec(S[q * qs + src_fast(g, c, fc, q)]);
-      } else {
+    for (int q = 0; q < Q; ++q) lam[q] = lam_next[q * qs + c.idx];
+    const LocalAdjoint a = adjoint_local(ph, ph.omega[c.b], pre, lam);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const Pull p = pull_general(g, ph, c, q);
-          pre[q] = (T)Cd::dec(S[p.q * qs + p.idx]);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < Q; ++q) lam[q] = (T)lam_next[q * qs + c.idx];
-      T sE = (T)0, sx, sy, sz;
-#pragma unroll
-      for (int q = 0; q < Q; ++q) sE += pre[q];
-      mirror_sums(pre, sx, sy, sz);
-      const Inv iv = invert(ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
-                            ph.c * (double)sz);
-      const EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
-      const LamEq L = lam_eq(lam_sums(lam, k), ph, iv.W, iv.bx, iv.by, iv.bz);
-      const GradEM gm = chain_moments(iv, L.Le, L.LW, L.Lbx, L.Lby, L.Lbz);
-      const double om = ph.omega[c.b];
-      const T om1 = (T)(1.0 - om);
-      const T aE = (T)(om * gm.gE);
-      const T ax = (T)(om * ph.c * gm.gx), ay = (T)(om * ph.c * gm.gy),
-              az = (T)(om * ph.c * gm.gz);
-      T dt = (T)0;
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        dt += lam[q] * (pre[q] - geq_dev(k, q));
-        T mu = om1 * lam[q] + aE;
-        if (EX[q] == 1) mu += ax;
-        if (EX[q] == -1) mu -= ax;
-        if (EY[q] == 1) mu += ay;
-        if (EY[q] == -1) mu -= ay;
-        if (EZ[q] == 1) mu += az;
-        if (EZ[q] == -1) mu -= az;
-        if (fast) {
-          lam_out[q * qs + src_fast(g, c, fc, q)] = (Lm)mu;
-        } else {
-          const Pull p = pull_general(g, ph, c, q);
-          if (p.bounce)
-            lam_out[OPP[q] * qs + c.idx] = (Lm)mu;
-          else if (p.clamped)
-            scratch[q * qs + c.idx] = (Lm)mu;
-          else
-            lam_out[q * qs + p.idx] = (Lm)mu;
-        }
-      }
-      acc[0] = om * om * (double)dt;
-    }
+    for (int q = 0; q < Q; ++q) lam_out[q * qs + src_fast(g, c, fc, q)] = adjoint_mu(a, lam[q], q);
+    acc[0] = a.dtau;
   }
   double out[5];
   block_sum<5>(acc, out);
   if (threadIdx.x == 0)
     for (int k2 = 0; k2 < 5; ++k2) part[(size_t)c.L * 5 + k2] = out[k2];
+}
+
+// General part of the reverse step, over the listed cells (list[i] = linear
+// cell index, -1 = padding; each instance's cells fill whole workgroups).
+// Zeroes the entries of lambda_t that no update writes, routes inflow cells'
+// lambda_{t+1} into the inflow gradient, and scatters through the general
+// pull (bounce-back to the cell's own opposite entry; clamped pulls into
+// `scratch`, indexed by the reading cell, for k_adjoint_faces).
+// part[blk][5] = (dtau, de_in, dbeta_in[3]) partials of this workgroup.
+template <int ST, class TC>
+__global__ __launch_bounds__(BLOCK) void k_adjoint_general(
+    const Geom g, const Phys ph, const int *__restrict__ list,
+    const typename Codec<ST, TC>::elem *__restrict__ S, const LamT *__restrict__ lam_next,
+    LamT *__restrict__ lam_out, LamT *__restrict__ scratch, double *__restrict__ part,
+    const InflowState in) {
+  using Cd = Codec<ST, TC>;
+  const size_t qs = (size_t)g.qs;
+  const int li = list[(size_t)blockIdx.x * BLOCK + threadIdx.x];
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (li >= 0) {
+    const Cell c = cell_at(g, li);
+    const bool solid = solid_at(ph, c.idx);
+    const bool inflow = !solid && is_inflow(g, c.x, c.y, c.z);
+    for (int p = 0; p < Q; ++p)
+      if (solid || !covered(g, ph, c, p, inflow)) lam_out[p * qs + c.idx] = 0.0;
+    if (inflow) {
+      double lam[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) lam[q] = lam_next[q * qs + c.idx];
+      const double g2 = 1.0 / (1.0 - (in.bx * in.bx + in.by * in.by + in.bz * in.bz));
+      const double W = (4.0 / 3.0) * in.e * g2;
+      const EqCoef<double> k = eq_coef<double>(ph, 0.0, in.e, W, in.bx, in.by, in.bz);
+      const LamEq L = lam_eq(lam_sums(lam, k), ph, W, in.bx, in.by, in.bz);
+      double gr[4];
+      eq_param_grad(L, in.e, in.bx, in.by, in.bz, gr);
+      for (int k2 = 0; k2 < 4; ++k2) acc[1 + k2] = gr[k2];
+    } else if (!solid) {
+      double pre[Q], lam[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const Pull p = pull_general(g, ph, c, q);
+        pre[q] = (double)Cd::dec(S[p.q * qs + p.idx]);
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) lam[q] = lam_next[q * qs + c.idx];
+      const LocalAdjoint a = adjoint_local(ph, ph.omega[c.b], pre, lam);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const double mu = adjoint_mu(a, lam[q], q);
+        const Pull p = pull_general(g, ph, c, q);
+        if (p.bounce)
+          lam_out[OPP[q] * qs + c.idx] = mu;
+        else if (p.clamped)
+          scratch[q * qs + c.idx] = mu;
+        else
+          lam_out[q * qs + p.idx] = mu;
+      }
+      acc[0] = a.dtau;
+    }
+  }
+  double out[5];
+  block_sum<5>(acc, out);
+  if (threadIdx.x == 0)
+    for (int k2 = 0; k2 < 5; ++k2) part[(size_t)blockIdx.x * 5 + k2] = out[k2];
+}
+
+// flag[cell] = 1 for the cells of the general reverse kernel (host builds the list).
+__global__ __launch_bounds__(BLOCK) void k_mark_general(const Geom g, const Phys ph,
+                                                        uint8_t *__restrict__ flag) {
+  const Cell c = decode_cell(g);
+  if (!c.active) return;
+  flag[c.idx] = adjoint_plain(g, ph, c) ? (uint8_t)0 : (uint8_t)1;
 }
 
 // Faces of non-periodic axes, flattened: face f = (axis, side) holds

@@ -31,6 +31,12 @@ struct rlb_solver {
   double *d_part;
   double *d_res;
   void *d_scratch;
+  // general-kernel cell list of the reverse step (built on first use)
+  int *d_glist;
+  int *d_gstart;  // [batch + 1] first workgroup of each instance in the list
+  double *d_part2;
+  int n_gblk;
+  bool glist_ready;
 };
 
 namespace {
@@ -228,7 +234,7 @@ rlb_status launch_moments(rlb_solver *h, double *n, double *e, double *beta, boo
                      S, S + (size_t)Q * h->g.qs, n, e, beta, sums ? h->d_part : nullptr);
   if (sums)
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(BLOCK), 0, h->stream, h->d_part, h->p.batch,
-                       h->g.nblk_per, h->d_res, nullptr, nullptr, nullptr);
+                       h->g.nblk_per, h->d_res, nullptr, nullptr, nullptr, nullptr, nullptr);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -243,23 +249,65 @@ rlb_status launch_fields_g(rlb_solver *h, const void *Sg, double *e, double *bet
   return RLB_OK;
 }
 
+// Cells of the general reverse kernel, in index order, each instance padded to
+// whole workgroups (-1 entries), so that every workgroup's partial sums belong
+// to one instance and their reduction order is fixed.
+rlb_status build_adjoint_list(rlb_solver *h) {
+  const size_t cells = (size_t)h->g.per * h->p.batch;
+  uint8_t *d_flag = nullptr;
+  RLB_HIP(hipMalloc(&d_flag, cells));
+  hipLaunchKernelGGL(k_mark_general, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+                     h->ph, d_flag);
+  std::vector<uint8_t> flag(cells);
+  hipError_t e = hipMemcpyAsync(flag.data(), d_flag, cells, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(d_flag);
+  if (e != hipSuccess) return fail(RLB_EDEVICE, std::string("adjoint list: ") + hipGetErrorString(e));
+  std::vector<int> list;
+  std::vector<int> start(h->p.batch + 1, 0);
+  for (int b = 0; b < h->p.batch; ++b) {
+    start[b] = (int)(list.size() / BLOCK);
+    for (int j = 0; j < h->g.per; ++j) {
+      const size_t i = (size_t)b * h->g.per + j;
+      if (flag[i]) list.push_back((int)i);
+    }
+    while (list.size() % BLOCK) list.push_back(-1);
+  }
+  start[h->p.batch] = (int)(list.size() / BLOCK);
+  h->n_gblk = start[h->p.batch];
+  if (h->n_gblk > 0) {
+    RLB_HIP(hipMalloc(&h->d_glist, list.size() * sizeof(int)));
+    RLB_HIP(hipMalloc(&h->d_gstart, start.size() * sizeof(int)));
+    RLB_HIP(hipMalloc(&h->d_part2, (size_t)h->n_gblk * 5 * sizeof(double)));
+    RLB_HIP(hipMemcpy(h->d_glist, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice));
+    RLB_HIP(hipMemcpy(h->d_gstart, start.data(), start.size() * sizeof(int),
+                      hipMemcpyHostToDevice));
+  }
+  h->glist_ready = true;
+  return RLB_OK;
+}
+
 template <int ST, class TC>
 rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_next, void *lam_out,
                           double *dtau, double *dbeta_in, double *de_in) {
   using El = typename Codec<ST, TC>::elem;
-  using Lm = typename Codec<ST, TC>::lam;
-  hipLaunchKernelGGL((k_adjoint<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
-                     (const El *)S, (const Lm *)lam_next, (Lm *)lam_out, (Lm *)h->d_scratch,
-                     h->d_part, h->in);
+  hipLaunchKernelGGL((k_adjoint<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+                     h->ph, (const El *)S, (const LamT *)lam_next, (LamT *)lam_out, h->d_part);
+  if (h->n_gblk > 0)
+    hipLaunchKernelGGL((k_adjoint_general<ST, TC>), dim3(h->n_gblk), dim3(BLOCK), 0, h->stream,
+                       h->g, h->ph, (const int *)h->d_glist, (const El *)S,
+                       (const LamT *)lam_next, (LamT *)lam_out, (LamT *)h->d_scratch, h->d_part2,
+                       h->in);
   if (h->faces.count > 0) {
     const long long nf = h->faces.start[h->faces.count];
-    hipLaunchKernelGGL(k_adjoint_faces<Lm>, dim3((unsigned)((nf + BLOCK - 1) / BLOCK)),
+    hipLaunchKernelGGL(k_adjoint_faces<LamT>, dim3((unsigned)((nf + BLOCK - 1) / BLOCK)),
                        dim3(BLOCK), 0, h->stream, h->g, h->ph, h->faces,
-                       (const Lm *)h->d_scratch, (Lm *)lam_out);
+                       (const LamT *)h->d_scratch, (LamT *)lam_out);
   }
   if (dtau || dbeta_in || de_in)
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(BLOCK), 0, h->stream, h->d_part, h->p.batch,
-                       h->g.nblk_per, nullptr, dtau, de_in, dbeta_in);
+                       h->g.nblk_per, nullptr, dtau, de_in, dbeta_in,
+                       h->n_gblk > 0 ? h->d_part2 : nullptr, (const int *)h->d_gstart);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -284,7 +332,7 @@ rlb_status launch_init_adjoint(rlb_solver *h, const double *e0, const double *be
                      h->ph, e0, beta0, (const Lm *)lam0, de0, db0, h->d_part, h->in);
   if (dbeta_in || de_in)
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(BLOCK), 0, h->stream, h->d_part, h->p.batch,
-                       h->g.nblk_per, nullptr, nullptr, de_in, dbeta_in);
+                       h->g.nblk_per, nullptr, nullptr, de_in, dbeta_in, nullptr, nullptr);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -325,6 +373,9 @@ void free_solver(rlb_solver *h) {
   if (h->d_part) (void)hipFree(h->d_part);
   if (h->d_res) (void)hipFree(h->d_res);
   if (h->d_scratch) (void)hipFree(h->d_scratch);
+  if (h->d_glist) (void)hipFree(h->d_glist);
+  if (h->d_gstart) (void)hipFree(h->d_gstart);
+  if (h->d_part2) (void)hipFree(h->d_part2);
   delete h;
 }
 
@@ -493,6 +544,10 @@ rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *la
     return fail(RLB_EINVAL, "adjoint buffers invalid");
   if (h->faces.count > 0 && !h->d_scratch)
     RLB_HIP(hipMalloc(&h->d_scratch, (size_t)Q * h->g.qs * h->lam_elem));
+  if (!h->glist_ready) {
+    rlb_status s = build_adjoint_list(h);
+    if (s != RLB_OK) return s;
+  }
   RLB_DISPATCH(h, launch_adjoint, h, g_state_t, lam_next, lam_out, dL_dtau, dL_dbeta_in,
                dL_de_in);
 }
