@@ -28,6 +28,34 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 Q = 19
+COUNTERS = os.path.join(ROOT, "profiles", "k_step_f64_sphere_200x100x100.md")
+KERNEL_SOURCES = ("kernels.hpp", "codec.hpp", "lattice.hpp", "rlb.hip")
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_0912_2913_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic(launch_seconds: float):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel
+    calibration), as GB/s over the measured launch time; None when the kernel
+    sources changed since the counters were taken."""
+    try:
+        line = next(l for l in open(COUNTERS) if l.startswith("counters: "))
+    except (OSError, StopIteration):
+        return None, None
+    rec = json.loads(line[len("counters: "):])
+    if rec.get("kernel_source_sha256_16") != kernel_source_sha():
+        return None, None
+    b = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return round(b / launch_seconds / 1e9, 1), b
 
 
 def algorithmic_bytes(s, elem: int, with_f: bool = True) -> dict:
@@ -40,7 +68,6 @@ def algorithmic_bytes(s, elem: int, with_f: bool = True) -> dict:
     if any(b == 2 for ax in s.bc for b in ax):
         for a, (lo, hi) in enumerate(s.bc):
             n = (s.nx, s.ny, s.nz)
-            area = cells // n[a]
             if lo == 2 or hi == 2:
                 plane = np.zeros(cells, bool).reshape(s.batch, s.nz, s.ny, s.nx)
                 sl = [slice(None)] * 4
@@ -206,6 +233,7 @@ def main():
     ms = 1e3 * dt / args.steps
     mlups = s.cells * args.steps / dt / 1e6
     achieved = ab["bytes"] / (dt / args.steps) / 1e9
+    traffic, traffic_bytes = counted_traffic(dt / args.steps)
     out = {
         "metric": "MLUPS (f+g D3Q19, 1 GPU) & %HBM roofline; adjoint/forward step time ratio",
         "value": round(mlups, 2),
@@ -225,12 +253,12 @@ def main():
                    "fluid_mlups": round(ab["updated_cells"] * args.steps / dt / 1e6, 2),
                    "unphysical_g_updates": counts[0], "nonpositive_f_eq_updates": counts[1]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_step<F64,f+g>",
-                     "bytes_per_launch": ab["bytes"]},
+                     "bytes_per_launch": ab["bytes"], "traffic_bytes_per_launch": traffic_bytes},
     }
     if args.copy_probe:
-        out["copy_probe_GBs"] = round(copy_probe(), 1)
+        out["copy_probe_GBs"] = round(copy_probe(), 1)  # calibration kernel for counter runs
     if not args.no_extras:
         extras = {}
         # mixed-precision storage on the 256^3 periodic box (same step kernel family)
@@ -249,8 +277,12 @@ def main():
                                             "speedup_vs_f64": round(t64 / dtb, 3)}
             del b
         out["mixed_precision_256cube"] = extras
-        out["adjoint_sphere_f64"] = {k: round(v, 4) for k, v in
-                                     bench_adjoint(s, min(args.steps, 200), 5).items()}
+        # reverse sweep per step (g-only recompute + adjoint step) against one forward step
+        for st in (ri.F64, ri.F32):
+            out["adjoint_sphere_" + ri.STORAGE_NAMES[st]] = {
+                k: round(v, 4) for k, v in
+                bench_adjoint(ri.sphere(storage=st), min(args.steps, 200), 5).items()}
+        out["copy_probe_GBs"] = round(copy_probe(), 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(out), flush=True)
