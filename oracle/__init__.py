@@ -43,14 +43,19 @@ _lp = ctypes.POINTER(ctypes.c_long)
 
 
 def lib():
-    """Load (building first if absent or stale) the oracle library."""
+    """Load (building first if absent or stale) the oracle library.  The
+    environment variable RLB_ORACLE_LIB selects another build of the same
+    source (the mutation tests load deliberately broken copies that way)."""
     global _lib
     if _lib is not None:
         return _lib
-    src = os.path.join(_HERE, "rlb_oracle.cpp")
-    if (not os.path.exists(_LIB_PATH)) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
-        _build.build()
-    L = ctypes.CDLL(_LIB_PATH)
+    path = os.environ.get("RLB_ORACLE_LIB")
+    if not path:
+        path = _LIB_PATH
+        src = os.path.join(_HERE, "rlb_oracle.cpp")
+        if (not os.path.exists(path)) or os.path.getmtime(path) < os.path.getmtime(src):
+            _build.build()
+    L = ctypes.CDLL(path)
     L.ora_lattice.argtypes = [_ip, _dp, _ip]
     L.ora_equilibria.argtypes = [ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double, _dp, _dp]
     L.ora_invert.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp]

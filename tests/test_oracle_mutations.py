@@ -1,0 +1,73 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle's source (a dropped term, a
+wrong sign, coefficient, index, root or direction), builds it on the CPU, and
+runs the oracle pin suite against that build: the suite must fail.  The real
+oracle is untouched; the broken copies live in a temporary directory.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "rlb_oracle.cpp")
+PINS = [os.path.join(ROOT, "tests", f) for f in
+        ("test_oracle_pins.py", "test_oracle_riemann.py", "test_oracle_gradients.py")]
+
+MUTATIONS = {
+    "drop_quadratic_term": ("6.0 * cu * cu / (cl2 * cl2)", "0.0 * cu * cu / (cl2 * cl2)"),
+    "flip_u2_sign": ("6.0 * cu * cu / (cl2 * cl2) -\n                2.0 * u2 / cl2",
+                     "6.0 * cu * cu / (cl2 * cl2) +\n                2.0 * u2 / cl2"),
+    "rest_constant": ("(4.0 - (2.0 + cl2)", "(3.0 - (2.0 + cl2)"),
+    "f_eq_coefficient": ("(1.0 + 3.0 * cu / cl2)", "(1.0 + 2.0 * cu / cl2)"),
+    "diagonal_weight": ("return 1.0 / 36.0;", "return 1.0 / 18.0;"),
+    "opposite_is_self": ("if (EV[p][0] == -EV[q][0] && EV[p][1] == -EV[q][1] && EV[p][2] == -EV[q][2]) return p;",
+                         "if (p == q) return p;"),
+    "push_instead_of_pull": ("L.resolve(a, c[a] - EV[q][a])", "L.resolve(a, c[a] + EV[q][a])"),
+    "wrong_root": ("T W = (2.0 * E + sqrt(disc)) / 3.0;", "T W = (2.0 * E - sqrt(disc)) / 3.0;"),
+    "relax_with_tau": ("og[q] = pg[q] - (1.0 / tau) * (pg[q] - geq[q]);",
+                       "og[q] = pg[q] - (1.0 / (tau + 0.5)) * (pg[q] - geq[q]);"),
+    "transposed_momentum_index": ("m0 += g[q] * (c_l * EV[q][0]);", "m0 += g[q] * (c_l * EV[q][1]);"),
+    "outflow_wraps": ("if (bc[a][0] == BC_PERIODIC) return", "if (bc[a][0] != BC_INFLOW) return"),
+    "gamma_sign": ("T gamma2 = 1.0 / (1.0 - u2);", "T gamma2 = 1.0 / (1.0 + u2);"),
+    "transposed_jacobian": ("for (int q = 0; q < Q; ++q) mu += lam[q] * J[q][p];",
+                            "for (int q = 0; q < Q; ++q) mu += lam[q] * J[p][q];"),
+    "inflow_not_held": ("      if (bc[a][0] == BC_INFLOW && c[a] == 0) return true;",
+                        "      if (bc[a][0] == BC_INFLOW && c[a] == 0 && false) return true;"),
+}
+
+
+@pytest.fixture(scope="module")
+def source():
+    return open(SRC).read()
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, source, tmp_path):
+    old, new = MUTATIONS[name]
+    assert source.count(old) >= 1, f"mutation site for {name} not found"
+    src = tmp_path / "mutant.cpp"
+    src.write_text(source.replace(old, new, 1))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o",
+                    str(lib), str(src)], check=True, capture_output=True)
+    env = dict(os.environ, RLB_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        *PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"no pin caught the planted mistake '{name}':\n{r.stdout[-2000:]}"
+
+
+def test_unmutated_copy_passes(source, tmp_path):
+    """Control: the same build of the unmodified source passes the pin suite, so a
+    failure above is the planted mistake's doing."""
+    src = tmp_path / "copy.cpp"
+    src.write_text(source)
+    lib = tmp_path / "libcopy.so"
+    subprocess.run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o",
+                    str(lib), str(src)], check=True, capture_output=True)
+    env = dict(os.environ, RLB_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        *PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stdout[-3000:]

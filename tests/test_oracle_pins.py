@@ -218,6 +218,26 @@ def test_uniform_flow_with_inflow_and_outflow_is_steady():
     assert np.abs(S - S0).max() <= 1e-13 * np.abs(S0).max()
 
 
+def test_inflow_plane_holds_the_inflow_state():
+    """A random interior next to an inflow face in a different state: the face
+    cells keep the inflow state's fields (n, e, beta) at every step."""
+    inflow = (0.9, 1.2, 0.15, 0.02, 0.0)
+    s = ri.random_state_setup(
+        9, 5, 6, seed=17, tau=[0.7],
+        bc=((ri.INFLOW, ri.OUTFLOW), (ri.PERIODIC, ri.PERIODIC), (ri.PERIODIC, ri.PERIODIC)),
+        inflow=inflow)
+    p = problem(s)
+    S = oracle.init(p, s.n0, s.e0, s.beta0)
+    face = (np.arange(s.cells) % s.nx) == 0
+    for _ in range(3):
+        oracle.run(p, S, 7)
+        n, e, b, _ = oracle.moments(p, S)
+        assert np.allclose(e[face], inflow[1], rtol=1e-13, atol=0)
+        assert np.allclose(n[face], inflow[0], rtol=1e-13, atol=0)
+        assert np.allclose(b[:, face], np.array(inflow[2:])[:, None], rtol=0, atol=1e-14)
+        assert np.abs(e[~face] - inflow[1]).max() > 1e-3  # the interior is another state
+
+
 # --------------------------------------------------------------------------- P-7
 @pytest.mark.parametrize("bc", ["outflow", "periodic"])
 def test_d3q19_line_equals_lumped_d1q3(bc):
