@@ -164,47 +164,57 @@ def bench_forward(s, steps, warmup):
     return dt, counts
 
 
-def bench_adjoint(s, steps, warmup):
-    """Per-step reverse-sweep cost: recompute of the g state (one g-only step)
-    plus one adjoint step, against one forward f+g step."""
+def bench_adjoint(s, T, warmup, reps=4):
+    """Cost of the gradient of a T-step run with sqrt(T) checkpointing, per step,
+    against one forward f+g step: the checkpointed g-only forward (one library
+    call per segment) plus the reverse sweep (per segment one recompute call and
+    one adjoint-sweep call; the parameter partials are reduced once at the end).
+    Also the adjoint kernels alone (one sweep over a segment's states)."""
     import torch
 
+    from paper_0912_2913_amd.autograd import GRun, segment_length
     from paper_0912_2913_amd.solver import Solver
 
     sv = Solver(s)
     sv.step(warmup)
-    fwd = time_steps(sv.step, steps, sv.stream)
-    g = [sv.g_state().clone(), sv.new_g()]
-    lam = [sv.new_lam().zero_(), sv.new_lam().zero_()]
-    lam[0][:, : sv.cells] = 1e-3
-    dtau = torch.zeros(sv.batch, dtype=torch.float64, device=sv.device)
-    dbi = torch.zeros(3, dtype=torch.float64, device=sv.device)
-    dei = torch.zeros(1, dtype=torch.float64, device=sv.device)
+    fwd = time_steps(sv.step, 50, sv.stream) / 50
+    S = segment_length(T)
+    run = GRun(sv, T, S)
+    dLde = torch.full((sv.cells,), 1e-3, dtype=torch.float64, device=sv.device)
+    dLdb = torch.full((3, sv.cells), 1e-3, dtype=torch.float64, device=sv.device)
 
-    def recompute(n):
-        for i in range(n):
-            sv.step_g(g[i % 2], g[(i + 1) % 2])
+    def g_forward(_):
+        for _r in range(reps):
+            run.forward(keep=True)
 
-    def adjoint(n):
-        for i in range(n):
-            sv.adjoint_step(g[0], lam[i % 2], lam[(i + 1) % 2], dtau, dbi, dei)
+    def g_backward(_):
+        for _r in range(reps):
+            run.backward(dLde, dLdb)
 
-    def both(n):
-        for i in range(n):
-            sv.step_g(g[0], g[1])
-            sv.adjoint_step(g[0], lam[i % 2], lam[(i + 1) % 2], dtau, dbi, dei)
+    run.forward(keep=True)
+    run.backward(dLde, dLdb)
+    t_gf = time_steps(g_forward, 0, sv.stream) / (reps * T)
+    t_bw = time_steps(g_backward, 0, sv.stream) / (reps * T)
+    seq = sv.new_g_seq(S)
+    seq[0].copy_(run.ckpt[0])
+    sv.trajectory_g(seq, S)
+    la, lb = sv.new_lam().zero_(), sv.new_lam().zero_()
+    la[:, : sv.cells] = 1e-3
 
-    recompute(2)
-    adjoint(2)
-    t_re = time_steps(recompute, steps, sv.stream)
-    t_adj = time_steps(adjoint, steps, sv.stream)
-    t_both = time_steps(both, steps, sv.stream)
+    def sweep(_):
+        for _r in range(reps):
+            sv.adjoint_sweep(seq, S, la, lb)
+
+    sweep(0)
+    t_sw = time_steps(sweep, 0, sv.stream) / (reps * S)
+    sv.adjoint_flush()
     sv.close()
-    del sv, g, lam
+    del sv, run, seq, la, lb
     torch.cuda.empty_cache()
-    return {"forward_ms": 1e3 * fwd / steps, "recompute_g_ms": 1e3 * t_re / steps,
-            "adjoint_ms": 1e3 * t_adj / steps, "recompute_plus_adjoint_ms": 1e3 * t_both / steps,
-            "ratio": t_both / fwd, "adjoint_kernel_ratio": t_adj / fwd}
+    return {"T": T, "segment": S, "forward_ms": 1e3 * fwd,
+            "checkpointed_g_forward_ms": 1e3 * t_gf, "reverse_sweep_ms": 1e3 * t_bw,
+            "adjoint_ms": 1e3 * t_sw, "ratio": t_bw / fwd, "gradient_ratio": (t_gf + t_bw) / fwd,
+            "adjoint_kernel_ratio": t_sw / fwd}
 
 
 def main():
@@ -277,11 +287,11 @@ def main():
                                             "speedup_vs_f64": round(t64 / dtb, 3)}
             del b
         out["mixed_precision_256cube"] = extras
-        # reverse sweep per step (g-only recompute + adjoint step) against one forward step
+        # gradient of a 60-step sphere run (the flow stays physical that long):
+        # reverse sweep per step (recompute + adjoint) against one forward step
         for st in (ri.F64, ri.F32):
             out["adjoint_sphere_" + ri.STORAGE_NAMES[st]] = {
-                k: round(v, 4) for k, v in
-                bench_adjoint(ri.sphere(storage=st), min(args.steps, 200), 5).items()}
+                k: round(v, 4) for k, v in bench_adjoint(ri.sphere(storage=st), 60, 5).items()}
         out["copy_probe_GBs"] = round(copy_probe(), 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s)

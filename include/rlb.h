@@ -118,8 +118,26 @@ rlb_status rlb_step(rlb_solver *h, int32_t nsteps);
 
 /* One step of the g population alone from g_src to g_dst (g blocks,
  * [19][q_stride], distinct).  f never enters (e, beta), so this is the exact
- * g part of rlb_step; used to recompute states in a reverse sweep. */
+ * g part of rlb_step; used to recompute states in a reverse sweep.  Entries
+ * of solid cells and of the padding beyond the cells are not written (no
+ * step ever reads them). */
 rlb_status rlb_step_g(rlb_solver *h, const void *g_src, void *g_dst);
+
+/* n (>= 0) steps of the g population alone, as n calls of rlb_step_g, from
+ * g_src to g_dst, ping-ponging through g_tmp so that the last step lands in
+ * g_dst (n = 0 copies g_src to g_dst).  g_src is read only; g_tmp (needed
+ * for n > 1) is overwritten; the three buffers are distinct g blocks.  Solid
+ * and padding entries as in rlb_step_g (copied when n = 0).  One
+ * call replaces n host round trips (the checkpointed forward sweep). */
+rlb_status rlb_advance_g(rlb_solver *h, const void *g_src, void *g_dst, void *g_tmp,
+                         int32_t n);
+
+/* Recompute a stretch of g states in place: g_seq holds n (>= 1) g blocks,
+ * block j at byte offset j * seq_stride (seq_stride >= the g block's bytes);
+ * block 0 is read, blocks 1 .. n-1 are overwritten with
+ * block j = rlb_step_g(block j-1).  Used to restore a segment of a
+ * checkpointed trajectory before its reverse sweep. */
+rlb_status rlb_trajectory_g(rlb_solver *h, void *g_seq, int64_t seq_stride, int32_t n);
 
 /* Device pointer of the buffer that holds the current state S_t. */
 rlb_status rlb_current(rlb_solver *h, void **state);
@@ -143,17 +161,41 @@ rlb_status rlb_fields_g(rlb_solver *h, const void *g_state, double *e, double *b
  * Returns RLB_EUNPHYSICAL when counts[0] > 0. */
 rlb_status rlb_counters(rlb_solver *h, int64_t counts[2]);
 
-/* One reverse step of the g population:
+/* One reverse step of the g population (the transpose of the linearised
+ * update of eq. lbe2 with its streaming and boundary rules):
  *   lam_out = (d S_{t+1} / d S_t)^T lam_next,
- * where S_{t+1} = step(S_t) with S_t = g_state_t (a g block).  lam_out is
- * overwritten; lam_next is not modified.  Also accumulates (+=, device
- * double): dL_dtau[batch] += lam_next . d S_{t+1} / d tau;
- * dL_dbeta_in[3], dL_de_in[1] += lam_next . d S_{t+1} / d(inflow state).
- * Any gradient pointer may be NULL.  Partial sums are reduced in a fixed
- * order, so results are bitwise reproducible. */
+ * where S_{t+1} = step(S_t) with S_t = g_state_t (a g block).  lam_next and
+ * lam_out are device double [19][q_stride] for every storage format, distinct;
+ * lam_out is overwritten, lam_next is not modified.  The step's parameter
+ * contributions,
+ *   dL_dtau[batch]  += lam_next . d S_{t+1} / d tau,
+ *   dL_dbeta_in[3], dL_de_in[1] += lam_next . d S_{t+1} / d(inflow state),
+ * are first added to per-workgroup partials held by the solver, in step
+ * order.  When any of the three (device double) gradient pointers is
+ * non-NULL the pending partials of this and all earlier unreduced steps are
+ * reduced into them (as rlb_adjoint_flush); with all three NULL they stay
+ * pending.  Reductions run in a fixed order, so results are bitwise
+ * reproducible and independent of how a sweep is split into calls. */
 rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *lam_next,
                             void *lam_out, double *dL_dtau, double *dL_dbeta_in,
                             double *dL_de_in);
+
+/* n (>= 0) reverse steps in one call: for j = n-1 down to 0, one
+ * rlb_adjoint_step with g_state_t = block j of g_seq (layout as in
+ * rlb_trajectory_g) and all gradient pointers NULL (the contributions stay
+ * pending).  lam_a holds the adjoint after the last state on entry; the
+ * steps ping-pong between lam_a and lam_b (distinct device double
+ * [19][q_stride] buffers) and *lam_result (host) receives whichever of the
+ * two holds lam after block 0 (lam_a when n is even). */
+rlb_status rlb_adjoint_sweep(rlb_solver *h, const void *g_seq, int64_t seq_stride, int32_t n,
+                             void *lam_a, void *lam_b, void **lam_result);
+
+/* Reduce the pending reverse-step partials (fixed order) and add them to
+ * dL_dtau[batch], dL_dbeta_in[3], dL_de_in[1] (device double, each may be
+ * NULL: that share is discarded).  Afterwards nothing is pending; a call
+ * with nothing pending does nothing. */
+rlb_status rlb_adjoint_flush(rlb_solver *h, double *dL_dtau, double *dL_dbeta_in,
+                             double *dL_de_in);
 
 /* Seed of a reverse sweep: lam_T = (d(e, beta) / d S_T)^T (dL_de, dL_dbeta)
  * per cell, with (e, beta) the fields of the g block g_state_T.  dL_de

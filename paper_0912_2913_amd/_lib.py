@@ -21,7 +21,8 @@ COLLIDE_AUTO, COLLIDE_F32, COLLIDE_F64 = 0, 1, 2
 EXPORTS = (
     "rlb_buffer_layout", "rlb_init", "rlb_step", "rlb_step_g", "rlb_current", "rlb_moments",
     "rlb_fields_g", "rlb_counters", "rlb_adjoint_step", "rlb_moments_adjoint", "rlb_init_adjoint",
-    "rlb_destroy", "rlb_status_string", "rlb_last_error",
+    "rlb_destroy", "rlb_status_string", "rlb_last_error", "rlb_advance_g", "rlb_trajectory_g",
+    "rlb_adjoint_sweep", "rlb_adjoint_flush",
 )
 
 
@@ -73,6 +74,11 @@ def lib():
     L.rlb_fields_g.argtypes = [vp, vp, vp, vp]
     L.rlb_counters.argtypes = [vp, i64p]
     L.rlb_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.rlb_advance_g.argtypes = [vp, vp, vp, vp, ctypes.c_int32]
+    L.rlb_trajectory_g.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32]
+    L.rlb_adjoint_sweep.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp,
+                                    ctypes.POINTER(vp)]
+    L.rlb_adjoint_flush.argtypes = [vp, vp, vp, vp]
     L.rlb_moments_adjoint.argtypes = [vp, vp, vp, vp, vp]
     L.rlb_init_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.rlb_destroy.argtypes = [vp]
@@ -82,7 +88,8 @@ def lib():
     L.rlb_last_error.restype = ctypes.c_char_p
     for name in ("rlb_buffer_layout", "rlb_init", "rlb_step", "rlb_step_g", "rlb_current",
                  "rlb_moments", "rlb_fields_g", "rlb_counters", "rlb_adjoint_step", "rlb_moments_adjoint",
-                 "rlb_init_adjoint", "rlb_destroy"):
+                 "rlb_init_adjoint", "rlb_destroy", "rlb_advance_g", "rlb_trajectory_g",
+                 "rlb_adjoint_sweep", "rlb_adjoint_flush"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

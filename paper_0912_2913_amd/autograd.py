@@ -50,45 +50,52 @@ class GRun:
         self.final: Optional[torch.Tensor] = None
 
     def forward(self, keep: bool = True):
-        """Run the T steps; with keep=False no checkpoint is stored (no reverse)."""
+        """Run the T steps; with keep=False no checkpoint is stored (no reverse).
+        One library call per segment (rlb_advance_g)."""
         sv = self.sv
-        a = sv.g_state().clone()  # S_0
-        b = sv.new_g()
-        self.ckpt = []
-        for t in range(self.T):
-            if keep and t % self.S == 0:
-                self.ckpt.append(a.clone())
-            sv.step_g(a, b)
-            a, b = b, a
-        if keep and self.T == 0:
-            self.ckpt.append(a.clone())
-        self.final = a
-        return sv.fields_g(a)
+        s0 = sv.g_state().clone()
+        tmp = sv.new_g()
+        if not keep:
+            self.ckpt = []
+            self.final = sv.new_g()
+            sv.advance_g(s0, self.final, tmp, self.T)
+            return sv.fields_g(self.final)
+        self.ckpt = [s0]
+        for k in range(self.K):
+            n = min(self.S, self.T - k * self.S)
+            dst = sv.new_g()
+            sv.advance_g(self.ckpt[k], dst, tmp, max(n, 0))
+            if k + 1 < self.K:
+                self.ckpt.append(dst)
+            else:
+                self.final = dst
+        return sv.fields_g(self.final)
 
     def backward(self, dLde: torch.Tensor, dLdb: torch.Tensor):
+        """Reverse sweep, one rlb_trajectory_g + one rlb_adjoint_sweep per
+        segment; the parameter partials stay pending across segments and are
+        reduced once, so the result does not depend on the segment length."""
         sv = self.sv
         dev = sv.device
         dtau = torch.zeros(sv.batch, dtype=torch.float64, device=dev)
         dbin = torch.zeros(3, dtype=torch.float64, device=dev)
         dein = torch.zeros(1, dtype=torch.float64, device=dev)
-        lam = [sv.new_lam(), sv.new_lam()]
-        sv.moments_adjoint(self.final, dLde.contiguous(), dLdb.contiguous(), lam[0])
-        cur = 0
-        seg_states = [sv.new_g() for _ in range(min(self.S, max(self.T, 1)))]
+        la, lb = sv.new_lam(), sv.new_lam()
+        sv.moments_adjoint(self.final, dLde.contiguous(), dLdb.contiguous(), la)
+        seq = sv.new_g_seq(min(self.S, max(self.T, 1)))
         for k in range(self.K - 1, -1, -1):
-            t0 = k * self.S
-            n = min(self.S, self.T - t0)
+            n = min(self.S, self.T - k * self.S)
             if n <= 0:
                 continue
-            seg_states[0].copy_(self.ckpt[k])
-            for j in range(1, n):
-                sv.step_g(seg_states[j - 1], seg_states[j])
-            for j in range(n - 1, -1, -1):
-                sv.adjoint_step(seg_states[j], lam[cur], lam[1 - cur], dtau, dbin, dein)
-                cur = 1 - cur
+            seq[0].copy_(self.ckpt[k])
+            sv.trajectory_g(seq, n)
+            res = sv.adjoint_sweep(seq, n, la, lb)
+            if res is lb:
+                la, lb = lb, la
+        sv.adjoint_flush(dtau, dbin, dein)
         de0 = torch.empty(sv.cells, dtype=torch.float64, device=dev)
         db0 = torch.empty((3, sv.cells), dtype=torch.float64, device=dev)
-        sv.init_adjoint(lam[cur], de0, db0, dbin, dein)
+        sv.init_adjoint(la, de0, db0, dbin, dein)
         return dtau, dein, dbin, de0, db0
 
 

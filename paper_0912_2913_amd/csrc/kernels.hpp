@@ -578,43 +578,48 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const Geom g, const Phys ph,
   }
 }
 
-// Per-instance, fixed-order reduction of [nblk][5] partials (one workgroup).
-//   res != null: res[b][k] = sum over the instance's blocks (k = 0..4);
-//   dtau != null: dtau[b] += sum of component 0;
-//   dinflow != null: dinflow[0..3] += sum over all blocks of components 1..4
-//   (order: e_in, beta_in x, y, z -> dL_de_in, dL_dbeta_in[3]).
-//   part2/start2 (optional): a second set of per-workgroup partials whose
-//   instance b owns workgroups [start2[b], start2[b+1]), added after part's.
-__global__ __launch_bounds__(BLOCK) void k_finish(const double *__restrict__ part, int batch,
-                                                  int nblk_per, double *__restrict__ res,
-                                                  double *__restrict__ dtau,
-                                                  double *__restrict__ de_in,
-                                                  double *__restrict__ dbeta_in,
+// Per-instance, fixed-order reduction of per-workgroup [5] partials: one
+// workgroup per instance b (gridDim.x = batch).  Instance b owns workgroups
+// [b*nblk_per, (b+1)*nblk_per) of `part` and, when part2 is given, workgroups
+// [start2[b], start2[b+1]) of `part2`.
+//   res  != null: res[b][k] = the instance's sums (k = 0..4);
+//   dtau != null: dtau[b] += component 0;
+//   inst != null: inst[b][0..3] = components 1..4 (inflow partials, summed over
+//                 instances in order by k_finish_inflow).
+__global__ __launch_bounds__(BLOCK) void k_finish(const double *__restrict__ part, int nblk_per,
                                                   const double *__restrict__ part2,
-                                                  const int *__restrict__ start2) {
-  double total[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = 0; b < batch; ++b) {
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int j = (int)threadIdx.x; j < nblk_per; j += BLOCK)
-      for (int k = 0; k < 5; ++k) v[k] += part[((size_t)b * nblk_per + j) * 5 + k];
-    if (part2)
-      for (int j = start2[b] + (int)threadIdx.x; j < start2[b + 1]; j += BLOCK)
-        for (int k = 0; k < 5; ++k) v[k] += part2[(size_t)j * 5 + k];
-    double out[5];
-    block_sum<5>(v, out);
-    if (threadIdx.x == 0) {
-      if (res)
-        for (int k = 0; k < 5; ++k) res[b * 5 + k] = out[k];
-      if (dtau) dtau[b] += out[0];
-      for (int k = 0; k < 4; ++k) total[k] += out[1 + k];
-    }
-    __syncthreads();
-  }
+                                                  const int *__restrict__ start2,
+                                                  double *__restrict__ res,
+                                                  double *__restrict__ dtau,
+                                                  double *__restrict__ inst) {
+  const int b = (int)blockIdx.x;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j = (int)threadIdx.x; j < nblk_per; j += BLOCK)
+    for (int k = 0; k < 5; ++k) v[k] += part[((size_t)b * nblk_per + j) * 5 + k];
+  if (part2)
+    for (int j = start2[b] + (int)threadIdx.x; j < start2[b + 1]; j += BLOCK)
+      for (int k = 0; k < 5; ++k) v[k] += part2[(size_t)j * 5 + k];
+  double out[5];
+  block_sum<5>(v, out);
   if (threadIdx.x == 0) {
-    if (de_in) de_in[0] += total[0];
-    if (dbeta_in)
-      for (int k = 0; k < 3; ++k) dbeta_in[k] += total[1 + k];
+    if (res)
+      for (int k = 0; k < 5; ++k) res[b * 5 + k] = out[k];
+    if (dtau) dtau[b] += out[0];
+    if (inst)
+      for (int k = 0; k < 4; ++k) inst[b * 4 + k] = out[1 + k];
   }
+}
+
+// de_in[0] += sum_b inst[b][0]; dbeta_in[k] += sum_b inst[b][1 + k] (in order).
+__global__ void k_finish_inflow(const double *__restrict__ inst, int batch,
+                                double *__restrict__ de_in, double *__restrict__ dbeta_in) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < batch; ++b)
+    for (int k = 0; k < 4; ++k) t[k] += inst[b * 4 + k];
+  if (de_in) de_in[0] += t[0];
+  if (dbeta_in)
+    for (int k = 0; k < 3; ++k) dbeta_in[k] += t[1 + k];
 }
 
 // ---------------------------------------------------------------------------
@@ -811,11 +816,14 @@ __device__ __forceinline__ double adjoint_mu(const LocalAdjoint &a, double lam, 
 // cells for which adjoint_plain() holds.  Each pulls pre from S_t, reads
 // lambda_{t+1}(x) and writes mu_q to lambda_t at the source of its pull q;
 // those targets cover every entry of lambda_t that no general cell writes.
-// part[L][5] = (dtau, 0, 0, 0, 0) partials of this workgroup.
+// part[L][5] = (dtau, 0, 0, 0, 0) partials of this workgroup, added to the
+// previous step's when accum is set (one reverse sweep accumulates per
+// workgroup in step order, then is reduced once).
 template <int ST, class TC>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(
     const Geom g, const Phys ph, const typename Codec<ST, TC>::elem *__restrict__ S,
-    const LamT *__restrict__ lam_next, LamT *__restrict__ lam_out, double *__restrict__ part) {
+    const LamT *__restrict__ lam_next, LamT *__restrict__ lam_out, double *__restrict__ part,
+    int accum) {
   using Cd = Codec<ST, TC>;
   const Cell c = decode_cell(g);
   const size_t qs = (size_t)g.qs;
@@ -835,7 +843,8 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
   double out[5];
   block_sum<5>(acc, out);
   if (threadIdx.x == 0)
-    for (int k2 = 0; k2 < 5; ++k2) part[(size_t)c.L * 5 + k2] = out[k2];
+    for (int k2 = 0; k2 < 5; ++k2)
+      part[(size_t)c.L * 5 + k2] = (accum ? part[(size_t)c.L * 5 + k2] : 0.0) + out[k2];
 }
 
 // General part of the reverse step, over the listed cells (list[i] = linear
@@ -844,13 +853,14 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
 // lambda_{t+1} into the inflow gradient, and scatters through the general
 // pull (bounce-back to the cell's own opposite entry; clamped pulls into
 // `scratch`, indexed by the reading cell, for k_adjoint_faces).
-// part[blk][5] = (dtau, de_in, dbeta_in[3]) partials of this workgroup.
+// part[blk][5] = (dtau, de_in, dbeta_in[3]) partials of this workgroup
+// (accumulated across steps like k_adjoint's).
 template <int ST, class TC>
 __global__ __launch_bounds__(BLOCK) void k_adjoint_general(
     const Geom g, const Phys ph, const int *__restrict__ list,
     const typename Codec<ST, TC>::elem *__restrict__ S, const LamT *__restrict__ lam_next,
     LamT *__restrict__ lam_out, LamT *__restrict__ scratch, double *__restrict__ part,
-    const InflowState in) {
+    const InflowState in, int accum) {
   using Cd = Codec<ST, TC>;
   const size_t qs = (size_t)g.qs;
   const int li = list[(size_t)blockIdx.x * BLOCK + threadIdx.x];
@@ -899,7 +909,9 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_general(
   double out[5];
   block_sum<5>(acc, out);
   if (threadIdx.x == 0)
-    for (int k2 = 0; k2 < 5; ++k2) part[(size_t)blockIdx.x * 5 + k2] = out[k2];
+    for (int k2 = 0; k2 < 5; ++k2)
+      part[(size_t)blockIdx.x * 5 + k2] =
+          (accum ? part[(size_t)blockIdx.x * 5 + k2] : 0.0) + out[k2];
 }
 
 // flag[cell] = 1 for the cells of the general reverse kernel (host builds the list).

@@ -28,7 +28,9 @@ struct rlb_solver {
   uint8_t *d_cls;
   void *d_in_eq;
   unsigned long long *d_counters;
-  double *d_part;
+  double *d_part;      // per-workgroup partials of moments / init-adjoint reductions
+  double *d_part_rev;  // reverse-step partials of the streaming kernel (accumulated)
+  double *d_inst;      // [batch][4] per-instance inflow partials
   double *d_res;
   void *d_scratch;
   // general-kernel cell list of the reverse step (built on first use)
@@ -37,6 +39,7 @@ struct rlb_solver {
   double *d_part2;
   int n_gblk;
   bool glist_ready;
+  bool rev_pending;  // reverse-step partials accumulated and not yet reduced
 };
 
 namespace {
@@ -233,8 +236,9 @@ rlb_status launch_moments(rlb_solver *h, double *n, double *e, double *beta, boo
   hipLaunchKernelGGL((k_moments<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
                      S, S + (size_t)Q * h->g.qs, n, e, beta, sums ? h->d_part : nullptr);
   if (sums)
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(BLOCK), 0, h->stream, h->d_part, h->p.batch,
-                       h->g.nblk_per, h->d_res, nullptr, nullptr, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_finish, dim3(h->p.batch), dim3(BLOCK), 0, h->stream, h->d_part,
+                       h->g.nblk_per, (const double *)nullptr, (const int *)nullptr, h->d_res,
+                       (double *)nullptr, (double *)nullptr);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -287,27 +291,40 @@ rlb_status build_adjoint_list(rlb_solver *h) {
   return RLB_OK;
 }
 
+// One reverse step; its partial sums are added to the pending ones.
 template <int ST, class TC>
-rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_next, void *lam_out,
-                          double *dtau, double *dbeta_in, double *de_in) {
+rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_next, void *lam_out) {
   using El = typename Codec<ST, TC>::elem;
+  const int accum = h->rev_pending ? 1 : 0;
   hipLaunchKernelGGL((k_adjoint<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
-                     h->ph, (const El *)S, (const LamT *)lam_next, (LamT *)lam_out, h->d_part);
+                     h->ph, (const El *)S, (const LamT *)lam_next, (LamT *)lam_out, h->d_part_rev,
+                     accum);
   if (h->n_gblk > 0)
     hipLaunchKernelGGL((k_adjoint_general<ST, TC>), dim3(h->n_gblk), dim3(BLOCK), 0, h->stream,
                        h->g, h->ph, (const int *)h->d_glist, (const El *)S,
                        (const LamT *)lam_next, (LamT *)lam_out, (LamT *)h->d_scratch, h->d_part2,
-                       h->in);
+                       h->in, accum);
   if (h->faces.count > 0) {
     const long long nf = h->faces.start[h->faces.count];
     hipLaunchKernelGGL(k_adjoint_faces<LamT>, dim3((unsigned)((nf + BLOCK - 1) / BLOCK)),
                        dim3(BLOCK), 0, h->stream, h->g, h->ph, h->faces,
                        (const LamT *)h->d_scratch, (LamT *)lam_out);
   }
-  if (dtau || dbeta_in || de_in)
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(BLOCK), 0, h->stream, h->d_part, h->p.batch,
-                       h->g.nblk_per, nullptr, dtau, de_in, dbeta_in,
-                       h->n_gblk > 0 ? h->d_part2 : nullptr, (const int *)h->d_gstart);
+  h->rev_pending = true;
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
+}
+
+// Reduce the pending reverse-step partials (fixed order) into the gradients.
+rlb_status flush_adjoint(rlb_solver *h, double *dtau, double *dbeta_in, double *de_in) {
+  if (!h->rev_pending) return RLB_OK;
+  hipLaunchKernelGGL(k_finish, dim3(h->p.batch), dim3(BLOCK), 0, h->stream, h->d_part_rev,
+                     h->g.nblk_per, h->n_gblk > 0 ? (const double *)h->d_part2 : nullptr,
+                     (const int *)h->d_gstart, (double *)nullptr, dtau, h->d_inst);
+  if (dbeta_in || de_in)
+    hipLaunchKernelGGL(k_finish_inflow, dim3(1), dim3(64), 0, h->stream, (const double *)h->d_inst,
+                       h->p.batch, de_in, dbeta_in);
+  h->rev_pending = false;
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -330,9 +347,13 @@ rlb_status launch_init_adjoint(rlb_solver *h, const double *e0, const double *be
   using Lm = typename Codec<ST, TC>::lam;
   hipLaunchKernelGGL((k_init_adjoint<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
                      h->ph, e0, beta0, (const Lm *)lam0, de0, db0, h->d_part, h->in);
-  if (dbeta_in || de_in)
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(BLOCK), 0, h->stream, h->d_part, h->p.batch,
-                       h->g.nblk_per, nullptr, nullptr, de_in, dbeta_in, nullptr, nullptr);
+  if (dbeta_in || de_in) {
+    hipLaunchKernelGGL(k_finish, dim3(h->p.batch), dim3(BLOCK), 0, h->stream, h->d_part,
+                       h->g.nblk_per, (const double *)nullptr, (const int *)nullptr,
+                       (double *)nullptr, (double *)nullptr, h->d_inst);
+    hipLaunchKernelGGL(k_finish_inflow, dim3(1), dim3(64), 0, h->stream, (const double *)h->d_inst,
+                       h->p.batch, de_in, dbeta_in);
+  }
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -371,6 +392,8 @@ void free_solver(rlb_solver *h) {
   if (h->d_in_eq) (void)hipFree(h->d_in_eq);
   if (h->d_counters) (void)hipFree(h->d_counters);
   if (h->d_part) (void)hipFree(h->d_part);
+  if (h->d_part_rev) (void)hipFree(h->d_part_rev);
+  if (h->d_inst) (void)hipFree(h->d_inst);
   if (h->d_res) (void)hipFree(h->d_res);
   if (h->d_scratch) (void)hipFree(h->d_scratch);
   if (h->d_glist) (void)hipFree(h->d_glist);
@@ -460,6 +483,10 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
     return cleanup_fail(e, "clear counters");
   if ((e = hipMalloc(&h->d_part, sizeof(double) * 5 * (size_t)h->g.nblk)) != hipSuccess)
     return cleanup_fail(e, "hipMalloc(partials)");
+  if ((e = hipMalloc(&h->d_part_rev, sizeof(double) * 5 * (size_t)h->g.nblk)) != hipSuccess)
+    return cleanup_fail(e, "hipMalloc(reverse partials)");
+  if ((e = hipMalloc(&h->d_inst, sizeof(double) * 4 * (size_t)p->batch)) != hipSuccess)
+    return cleanup_fail(e, "hipMalloc(instance partials)");
   if ((e = hipMalloc(&h->d_res, sizeof(double) * 5 * (size_t)p->batch)) != hipSuccess)
     return cleanup_fail(e, "hipMalloc(results)");
   if (solid) {
@@ -536,20 +563,97 @@ rlb_status rlb_counters(rlb_solver *h, int64_t counts[2]) {
   return c[0] > 0 ? RLB_EUNPHYSICAL : RLB_OK;
 }
 
-rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *lam_next,
-                            void *lam_out, double *dL_dtau, double *dL_dbeta_in,
-                            double *dL_de_in) {
-  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
-  if (!g_state_t || !lam_next || !lam_out || lam_next == lam_out)
-    return fail(RLB_EINVAL, "adjoint buffers invalid");
+// Lazily allocated reverse-step resources (clamped-pull scratch, general-cell list).
+static rlb_status prepare_adjoint(rlb_solver *h) {
   if (h->faces.count > 0 && !h->d_scratch)
     RLB_HIP(hipMalloc(&h->d_scratch, (size_t)Q * h->g.qs * h->lam_elem));
   if (!h->glist_ready) {
     rlb_status s = build_adjoint_list(h);
     if (s != RLB_OK) return s;
   }
-  RLB_DISPATCH(h, launch_adjoint, h, g_state_t, lam_next, lam_out, dL_dtau, dL_dbeta_in,
-               dL_de_in);
+  return RLB_OK;
+}
+
+rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *lam_next,
+                            void *lam_out, double *dL_dtau, double *dL_dbeta_in,
+                            double *dL_de_in) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (!g_state_t || !lam_next || !lam_out || lam_next == lam_out)
+    return fail(RLB_EINVAL, "adjoint buffers invalid");
+  rlb_status s = prepare_adjoint(h);
+  if (s != RLB_OK) return s;
+  auto launch = [&]() -> rlb_status {
+    RLB_DISPATCH(h, launch_adjoint, h, g_state_t, lam_next, lam_out);
+  };
+  s = launch();
+  if (s != RLB_OK) return s;
+  if (dL_dtau || dL_dbeta_in || dL_de_in) return flush_adjoint(h, dL_dtau, dL_dbeta_in, dL_de_in);
+  return RLB_OK;
+}
+
+rlb_status rlb_adjoint_sweep(rlb_solver *h, const void *g_seq, int64_t seq_stride, int32_t n,
+                             void *lam_a, void *lam_b, void **lam_result) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (n < 0 || !lam_a || !lam_b || lam_a == lam_b || !lam_result || (n > 0 && !g_seq) ||
+      seq_stride < 0)
+    return fail(RLB_EINVAL, "adjoint sweep arguments invalid");
+  rlb_status s = prepare_adjoint(h);
+  if (s != RLB_OK) return s;
+  void *cur = lam_a, *nxt = lam_b;
+  for (int j = n - 1; j >= 0; --j) {
+    const void *S = (const char *)g_seq + (size_t)j * (size_t)seq_stride;
+    auto launch = [&]() -> rlb_status {
+      RLB_DISPATCH(h, launch_adjoint, h, S, (const void *)cur, nxt);
+    };
+    s = launch();
+    if (s != RLB_OK) return s;
+    void *t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  *lam_result = cur;
+  return RLB_OK;
+}
+
+rlb_status rlb_adjoint_flush(rlb_solver *h, double *dL_dtau, double *dL_dbeta_in,
+                             double *dL_de_in) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  return flush_adjoint(h, dL_dtau, dL_dbeta_in, dL_de_in);
+}
+
+rlb_status rlb_advance_g(rlb_solver *h, const void *g_src, void *g_dst, void *g_tmp, int32_t n) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (n < 0 || !g_src || !g_dst || g_src == g_dst || (n > 1 && (!g_tmp || g_tmp == g_src ||
+                                                                 g_tmp == g_dst)))
+    return fail(RLB_EINVAL, "advance arguments invalid");
+  if (n == 0) {
+    RLB_HIP(hipMemcpyAsync(g_dst, g_src, (size_t)Q * h->g.qs * h->elem,
+                           hipMemcpyDeviceToDevice, h->stream));
+    return RLB_OK;
+  }
+  const void *cur = g_src;
+  for (int i = 0; i < n; ++i) {
+    void *next = ((n - 1 - i) % 2 == 0) ? g_dst : g_tmp;  // the last step lands in g_dst
+    auto launch = [&]() -> rlb_status { RLB_DISPATCH(h, launch_step_g, h, cur, next); };
+    rlb_status s = launch();
+    if (s != RLB_OK) return s;
+    cur = next;
+  }
+  return RLB_OK;
+}
+
+rlb_status rlb_trajectory_g(rlb_solver *h, void *g_seq, int64_t seq_stride, int32_t n) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  const int64_t need = (int64_t)Q * h->g.qs * (int64_t)h->elem;
+  if (n < 1 || !g_seq || seq_stride < need) return fail(RLB_EINVAL, "trajectory arguments invalid");
+  for (int j = 1; j < n; ++j) {
+    const void *src = (const char *)g_seq + (size_t)(j - 1) * (size_t)seq_stride;
+    void *dst = (char *)g_seq + (size_t)j * (size_t)seq_stride;
+    auto launch = [&]() -> rlb_status { RLB_DISPATCH(h, launch_step_g, h, src, dst); };
+    rlb_status s = launch();
+    if (s != RLB_OK) return s;
+  }
+  return RLB_OK;
 }
 
 rlb_status rlb_moments_adjoint(rlb_solver *h, const void *g_state_T, const double *dL_de,

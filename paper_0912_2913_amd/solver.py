@@ -101,6 +101,46 @@ class Solver:
     def step_g(self, g_src: torch.Tensor, g_dst: torch.Tensor):
         check(_lib.lib().rlb_step_g(self.h, _ptr(g_src), _ptr(g_dst)), "rlb_step_g")
 
+    def advance_g(self, g_src: torch.Tensor, g_dst: torch.Tensor, g_tmp: torch.Tensor, n: int):
+        """n g-only steps from g_src into g_dst (g_tmp: ping-pong buffer)."""
+        check(_lib.lib().rlb_advance_g(self.h, _ptr(g_src), _ptr(g_dst), _ptr(g_tmp), int(n)),
+              "rlb_advance_g")
+
+    def new_g_seq(self, n: int) -> torch.Tensor:
+        """n contiguous g blocks, [n][19][q_stride]."""
+        return torch.empty((n, Q, self.q_stride), dtype=self.dtype, device=self.device)
+
+    def _seq_stride(self, g_seq: torch.Tensor) -> int:
+        if g_seq.dim() != 3 or g_seq.shape[1:] != (Q, self.q_stride) or not g_seq.is_contiguous():
+            raise ValueError("g_seq must be a contiguous [n][19][q_stride] tensor")
+        if g_seq.dtype != self.dtype:
+            raise ValueError("g_seq dtype does not match the storage format")
+        return Q * self.q_stride * g_seq.element_size()
+
+    def trajectory_g(self, g_seq: torch.Tensor, n: int):
+        """Blocks 1 .. n-1 of g_seq recomputed from block 0."""
+        if not 1 <= n <= g_seq.shape[0]:
+            raise ValueError("n out of range for g_seq")
+        check(_lib.lib().rlb_trajectory_g(self.h, _ptr(g_seq), self._seq_stride(g_seq), int(n)),
+              "rlb_trajectory_g")
+
+    def adjoint_sweep(self, g_seq: torch.Tensor, n: int, lam_a: torch.Tensor,
+                      lam_b: torch.Tensor) -> torch.Tensor:
+        """n reverse steps over blocks n-1 .. 0 of g_seq, starting from lam_a;
+        returns the buffer (lam_a or lam_b) holding the result.  Parameter
+        contributions stay pending until adjoint_flush."""
+        if not 0 <= n <= g_seq.shape[0]:
+            raise ValueError("n out of range for g_seq")
+        res = ctypes.c_void_p()
+        check(_lib.lib().rlb_adjoint_sweep(self.h, _ptr(g_seq), self._seq_stride(g_seq), int(n),
+                                           _ptr(lam_a), _ptr(lam_b), ctypes.byref(res)),
+              "rlb_adjoint_sweep")
+        return lam_a if res.value == lam_a.data_ptr() else lam_b
+
+    def adjoint_flush(self, dtau=None, dbeta_in=None, de_in=None):
+        check(_lib.lib().rlb_adjoint_flush(self.h, _ptr(dtau), _ptr(dbeta_in), _ptr(de_in)),
+              "rlb_adjoint_flush")
+
     def state(self) -> torch.Tensor:
         """The buffer holding the current state, [2][19][q_stride] (a view, not a copy)."""
         p = ctypes.c_void_p()

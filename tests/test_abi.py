@@ -115,4 +115,8 @@ def test_null_handle_is_rejected(L):
     assert lib.rlb_step(None, 1) == L.RLB_EINVAL
     assert lib.rlb_moments(None, None, None, None, None) == L.RLB_EINVAL
     assert lib.rlb_adjoint_step(None, None, None, None, None, None, None) == L.RLB_EINVAL
+    assert lib.rlb_advance_g(None, None, None, None, 1) == L.RLB_EINVAL
+    assert lib.rlb_trajectory_g(None, None, 0, 1) == L.RLB_EINVAL
+    assert lib.rlb_adjoint_sweep(None, None, 0, 1, None, None, None) == L.RLB_EINVAL
+    assert lib.rlb_adjoint_flush(None, None, None, None) == L.RLB_EINVAL
     assert lib.rlb_destroy(None) == L.RLB_OK

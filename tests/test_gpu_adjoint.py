@@ -199,3 +199,146 @@ def test_gradient_matches_central_differences_fp64():
     v = np.random.default_rng(4).standard_normal(s.cells) * 1e-2
     fd = (loss(s.tau, s.e0 + h * v) - loss(s.tau, s.e0 - h * v)) / (2 * h)
     assert float((e0.grad.cpu().numpy() * v).sum()) == pytest.approx(fd, rel=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Loop entry points: one call per segment instead of one per step.
+
+def bits(t: torch.Tensor) -> torch.Tensor:
+    """Bit pattern of a tensor (bitwise comparison that also holds for NaN
+    payloads in never-written padding)."""
+    return t.contiguous().view(torch.uint8)
+
+
+def _state_after(s, steps):
+    p = problem(s)
+    S = oracle.init(p, s.n0, s.e0, s.beta0)
+    oracle.run(p, S, steps)
+    return np.ascontiguousarray(S[1])
+
+
+@pytest.mark.parametrize("storage", [ri.F64, ri.F32DEV, ri.BF16DEV])
+def test_advance_and_trajectory_equal_step_g_chain_bitwise(storage):
+    from dataclasses import replace
+
+    from paper_0912_2913_amd.solver import Solver
+
+    s = replace(setups()["inflow_outflow_obstacle"], storage=storage, e_ref=1.0)
+    sv = Solver(s)
+    fl = torch.as_tensor(s.solid == 0, device=sv.device)  # solid entries are never written
+    g0 = sv.g_state().clone()
+    chain = [g0.clone()]
+    for _ in range(6):
+        nxt = sv.new_g()
+        sv.step_g(chain[-1], nxt)
+        chain.append(nxt)
+    tmp = sv.new_g()
+    for n in (0, 1, 2, 5, 6):
+        dst = sv.new_g().fill_(7)
+        sv.advance_g(g0, dst, tmp, n)
+        assert torch.equal(bits(dst[:, : sv.cells][:, fl]), bits(chain[n][:, : sv.cells][:, fl])), n
+    assert torch.equal(bits(g0), bits(chain[0]))  # the source is read only
+    seq = sv.new_g_seq(7)
+    seq[0].copy_(g0)
+    seq[1:].fill_(3)
+    sv.trajectory_g(seq, 5)
+    for j in range(5):
+        assert torch.equal(bits(seq[j, :, : sv.cells][:, fl]), bits(chain[j][:, : sv.cells][:, fl])), j
+    assert bool((seq[5:] == 3).all())  # blocks beyond n untouched
+    sv.close()
+
+
+@pytest.mark.parametrize("name", ["inflow_outflow_obstacle", "tube_batch"])
+def test_adjoint_sweep_equals_pending_adjoint_steps(name):
+    """A sweep of n steps = n rlb_adjoint_step calls whose partials stay pending
+    until the last call passes gradient pointers: lambda and gradients bitwise.
+    Against steps flushed one by one: lambda bitwise, gradients to rounding."""
+    from paper_0912_2913_amd.solver import Solver
+
+    s = setups()[name]
+    sv = Solver(s)
+    n = 5
+    seq = sv.new_g_seq(n)
+    seq[0].copy_(upload_g(sv, _state_after(s, 2)))
+    sv.trajectory_g(seq, n)
+    rng = np.random.default_rng(11)
+    lam_T = upload_lam(sv, rng.standard_normal((19, s.cells)))
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device=sv.device)
+
+    la, lb = lam_T.clone(), torch.full_like(lam_T, float("nan"))
+    res = sv.adjoint_sweep(seq, n, la, lb)
+    assert res is (la if n % 2 == 0 else lb)
+    g_sw = (z(s.batch), z(3), z(1))
+    sv.adjoint_flush(*g_sw)
+
+    a, b = lam_T.clone(), torch.full_like(lam_T, float("nan"))
+    g_pe = (z(s.batch), z(3), z(1))
+    for j in range(n - 1, -1, -1):
+        sv.adjoint_step(seq[j], a, b, *(g_pe if j == 0 else (None, None, None)))
+        a, b = b, a
+    assert torch.equal(a[:, : sv.cells], res[:, : sv.cells])
+    for x, y in zip(g_sw, g_pe):
+        assert torch.equal(x, y)
+
+    a, b = lam_T.clone(), torch.full_like(lam_T, float("nan"))
+    g_ea = (z(s.batch), z(3), z(1))
+    for j in range(n - 1, -1, -1):
+        sv.adjoint_step(seq[j], a, b, *g_ea)
+        a, b = b, a
+    for x, y in zip(g_sw, g_ea):
+        x, y = x.cpu().numpy(), y.cpu().numpy()
+        assert np.abs(x - y).max() <= 1e-13 * max(np.abs(y).max(), 1e-300)
+    sv.close()
+
+
+def test_flush_discards_and_empty_flush_is_a_no_op():
+    from paper_0912_2913_amd.solver import Solver
+
+    s = setups()["inflow_outflow_obstacle"]
+    g = None
+    rng = np.random.default_rng(12)
+    lam = rng.standard_normal((19, s.cells))
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda:0")
+
+    def one_step(sv, pending_first):
+        nonlocal g
+        g = upload_g(sv, _state_after(s, 1)) if g is None else g
+        ln, lo = upload_lam(sv, lam), sv.new_lam()
+        if pending_first:
+            sv.adjoint_step(g, ln, lo)  # pending ...
+            sv.adjoint_flush()          # ... and discarded
+        out = (z(s.batch), z(3), z(1))
+        sv.adjoint_flush(*out)          # nothing pending: no change
+        assert all(float(t.abs().max()) == 0.0 for t in out)
+        sv.adjoint_step(g, ln, lo, *out)
+        return [t.cpu().numpy() for t in out]
+
+    sv1 = Solver(s)
+    r1 = one_step(sv1, True)
+    sv1.close()
+    sv2 = Solver(s)
+    r2 = one_step(sv2, False)
+    sv2.close()
+    for x, y in zip(r1, r2):
+        assert np.array_equal(x, y)
+
+
+def test_loop_entry_points_reject_bad_arguments():
+    from paper_0912_2913_amd._lib import RLBError
+    from paper_0912_2913_amd.solver import Solver
+
+    s = setups()["outflow_corners"]
+    sv = Solver(s)
+    a, b, c = sv.new_g(), sv.new_g(), sv.new_g()
+    for args in ((a, b, c, -1), (a, a, c, 2), (a, b, a, 2), (a, b, b, 2)):
+        with pytest.raises(RLBError):
+            sv.advance_g(*args)
+    seq = sv.new_g_seq(3)
+    with pytest.raises(ValueError):
+        sv.trajectory_g(seq, 0)
+    with pytest.raises(ValueError):
+        sv.trajectory_g(seq, 4)
+    la = sv.new_lam()
+    with pytest.raises(RLBError):
+        sv.adjoint_sweep(seq, 2, la, la)
+    sv.close()
