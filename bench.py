@@ -198,8 +198,8 @@ def bench_adjoint(s, T, warmup, reps=4):
     seq = sv.new_g_seq(S)
     seq[0].copy_(run.ckpt[0])
     sv.trajectory_g(seq, S)
-    la, lb = sv.new_lam().zero_(), sv.new_lam().zero_()
-    la[:, : sv.cells] = 1e-3
+    la = sv.pack(torch.full((Q, sv.cells), 1e-3, dtype=torch.float64), dtype=sv.lam_dtype)
+    lb = sv.new_lam().zero_()
 
     def sweep(_):
         for _r in range(reps):

@@ -16,9 +16,14 @@
  *    = dx, one step = dt = dx / c_l; tau is in units of dt (omega = 1/tau).
  *  - Cell index: cell = ((b*nz + z)*ny + y)*nx + x, x fastest; b = instance.
  *    cells = batch*nz*ny*nx.
- *  - Population buffer ("state"): [pop][q][q_stride] elements, pop 0 = f,
- *    pop 1 = g, q = 0..18, q_stride = cells rounded up to a multiple of 64
- *    (see rlb_buffer_layout).  A "g block" is the [19][q_stride] second half.
+ *  - Population buffer ("state"): two population blocks, f then g, of
+ *    19*q_stride elements each, q_stride = cells rounded up to a multiple of
+ *    64 (see rlb_buffer_layout).  Inside a block the cells are grouped in
+ *    bricks of 64 consecutive cells, each brick holding its 19 directions
+ *    one after another: element (q, cell) of a block is at
+ *      (cell / 64) * 19 * 64 + q * 64 + cell % 64,
+ *    and the g block starts at element 19*q_stride.  A "g block" is that
+ *    second half on its own (any g state, e.g. a checkpoint).
  *    Element type by storage: RLB_F64 double; RLB_F32 float; RLB_F32DEV float,
  *    RLB_F16DEV IEEE binary16, RLB_BF16DEV bfloat16, the *DEV forms holding
  *    the deviation S_i - R_i from the rest equilibrium R at (n_ref, e_ref).
@@ -32,7 +37,8 @@
  *    clamped into the domain); INFLOW holds the face plane at the equilibrium
  *    of (inflow_n, inflow_e, inflow_beta).  Solid cells reflect by half-way
  *    bounce-back and are never updated.
- *  - Adjoint buffers ("lambda"): [19][q_stride] double, for every storage.
+ *  - Adjoint buffers ("lambda"): one block in the same brick layout, double
+ *    for every storage.
  *  - Device pointers address memory on the solver's device; every call that
  *    launches work is asynchronous on the stream given to rlb_init unless its
  *    comment says it synchronises.  Nothing throws across the ABI.
@@ -88,8 +94,9 @@ typedef struct {
   int32_t collide;           /* rlb_collide                                      */
 } rlb_params;
 
-/* Layout of one population buffer for these parameters: q_stride elements per
- * direction and the byte size of a full f+g buffer (2*19*q_stride*elem).
+/* Layout of one population buffer for these parameters: q_stride (cells
+ * rounded up to 64, i.e. 64 * number of bricks) and the byte size of a full
+ * f+g buffer (2*19*q_stride*elem).
  * Either output may be NULL.  Host-only, no device work. */
 rlb_status rlb_buffer_layout(const rlb_params *p, int64_t *q_stride, int64_t *state_bytes);
 
@@ -117,10 +124,11 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
 rlb_status rlb_step(rlb_solver *h, int32_t nsteps);
 
 /* One step of the g population alone from g_src to g_dst (g blocks,
- * [19][q_stride], distinct).  f never enters (e, beta), so this is the exact
- * g part of rlb_step; used to recompute states in a reverse sweep.  Entries
- * of solid cells and of the padding beyond the cells are not written (no
- * step ever reads them). */
+ * 19*q_stride elements, distinct).  f never enters (e, beta), so this is the exact
+ * g part of rlb_step; used to recompute states in a reverse sweep.  Solid
+ * cells' entries are written with the value rlb_init gives them (encoded
+ * zero), inflow-plane cells with the inflow equilibrium; the padding beyond
+ * the cells is not written (no step reads it). */
 rlb_status rlb_step_g(rlb_solver *h, const void *g_src, void *g_dst);
 
 /* n (>= 0) steps of the g population alone, as n calls of rlb_step_g, from
@@ -165,7 +173,7 @@ rlb_status rlb_counters(rlb_solver *h, int64_t counts[2]);
  * update of eq. lbe2 with its streaming and boundary rules):
  *   lam_out = (d S_{t+1} / d S_t)^T lam_next,
  * where S_{t+1} = step(S_t) with S_t = g_state_t (a g block).  lam_next and
- * lam_out are device double [19][q_stride] for every storage format, distinct;
+ * lam_out are device double blocks (brick layout) for every storage, distinct;
  * lam_out is overwritten, lam_next is not modified.  The step's parameter
  * contributions,
  *   dL_dtau[batch]  += lam_next . d S_{t+1} / d tau,
@@ -185,7 +193,7 @@ rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *la
  * rlb_trajectory_g) and all gradient pointers NULL (the contributions stay
  * pending).  lam_a holds the adjoint after the last state on entry; the
  * steps ping-pong between lam_a and lam_b (distinct device double
- * [19][q_stride] buffers) and *lam_result (host) receives whichever of the
+ * lambda blocks) and *lam_result (host) receives whichever of the
  * two holds lam after block 0 (lam_a when n is even). */
 rlb_status rlb_adjoint_sweep(rlb_solver *h, const void *g_seq, int64_t seq_stride, int32_t n,
                              void *lam_a, void *lam_b, void **lam_result);

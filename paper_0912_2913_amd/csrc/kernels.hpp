@@ -65,6 +65,26 @@ struct Geom {
   int alo[3], ahi[3];  // adjoint fast range per axis (whole axis if periodic)
 };
 
+// Values the inflow plane holds (f then g, storage format), passed by value
+// so that they are read from kernel-argument memory through the scalar unit.
+template <class El>
+struct HeldEq {
+  El v[2 * Q];
+};
+
+// Population block layout: bricks of 64 consecutive cells, each holding its
+// 19 directions one after another, so element (q, cell i) lives at
+//   (i / 64) * 19 * 64 + q * 64 + i % 64.
+// A wavefront's 19 reads or writes of one population then fall in one
+// 19 * 64-element span (for unshifted directions) instead of 19 slices one
+// population-plane apart, which keeps HBM page locality; the f block is
+// followed by the g block (offset 19 * qs).  qs = cells rounded up to 64.
+constexpr int BRICK = 64;
+
+__device__ __forceinline__ size_t at(int q, long long i) {
+  return (size_t)(i >> 6) * (size_t)(Q * BRICK) + (size_t)(q * BRICK) + (size_t)(i & (BRICK - 1));
+}
+
 struct Phys {
   double c, inv_c, inv_c2, k0;  // k0 = 3 - 2/c_l^2
   double n_ref, e_ref;          // zero unless the storage holds deviations
@@ -352,46 +372,40 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *out) {
   }
 }
 
-// Pull the 19 values of one population for cell c (decoded to the compute
-// type): branch-free face corrections unless a neighbour is solid.
+// Element offset of the pull of direction q for cell c: the resolved source
+// (wrap / clamp by the branch-free face corrections), or, for a cell next to
+// a solid (near) whose source is solid, its own opposite population
+// (half-way bounce-back).  Both candidates have compile-time directions after
+// unrolling; only near lanes read the source's class byte.
+__device__ __forceinline__ size_t pull_at(const Geom &g, const Phys &ph, const Cell &c,
+                                          const FaceCorr &fc, bool near, int q) {
+  const long long s = src_fast(g, c, fc, q);
+  if (near && (ph.cls[s] & CLS_SOLID)) return at(OPP[q], c.idx);
+  return at(q, s);
+}
+
+// Pull the 19 values of one population for cell c (decoded to the compute type).
 template <class Cd>
 __device__ __forceinline__ void gather(const Geom &g, const Phys &ph, const Cell &c, bool near,
-                                       const typename Cd::elem *__restrict__ P, size_t qs,
+                                       const typename Cd::elem *__restrict__ P,
                                        typename Cd::calc (&v)[Q]) {
-  if (!near) {
-    const FaceCorr fc = face_corr(g, c);
+  const FaceCorr fc = face_corr(g, c);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) v[q] = Cd::dec(P[q * qs + src_fast(g, c, fc, q)]);
-  } else {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const Pull p = pull_general(g, ph, c, q);
-      v[q] = Cd::dec(P[p.q * qs + p.idx]);
-    }
-  }
+  for (int q = 0; q < Q; ++q) v[q] = Cd::dec(P[pull_at(g, ph, c, fc, near, q)]);
 }
 
 // Both populations of cell c, pulled in one pass (same sources for f and g).
 template <class Cd>
 __device__ __forceinline__ void gather2(const Geom &g, const Phys &ph, const Cell &c, bool near,
                                         const typename Cd::elem *__restrict__ G,
-                                        const typename Cd::elem *__restrict__ F, size_t qs,
+                                        const typename Cd::elem *__restrict__ F,
                                         typename Cd::calc (&vg)[Q], typename Cd::calc (&vf)[Q]) {
-  if (!near) {
-    const FaceCorr fc = face_corr(g, c);
+  const FaceCorr fc = face_corr(g, c);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const long long s = src_fast(g, c, fc, q);
-      vg[q] = Cd::dec(G[q * qs + s]);
-      vf[q] = Cd::dec(F[q * qs + s]);
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const Pull p = pull_general(g, ph, c, q);
-      vg[q] = Cd::dec(G[p.q * qs + p.idx]);
-      vf[q] = Cd::dec(F[p.q * qs + p.idx]);
-    }
+  for (int q = 0; q < Q; ++q) {
+    const size_t o = pull_at(g, ph, c, fc, near, q);
+    vg[q] = Cd::dec(G[o]);
+    vf[q] = Cd::dec(F[o]);
   }
 }
 
@@ -404,39 +418,39 @@ __device__ __forceinline__ void stream_store(El *p, El v) {
 
 // ---------------------------------------------------------------------------
 // Forward stream-collide step.  DO_F = false updates the g population only
-// (src/dst then address g blocks).
-template <int ST, class TC, bool DO_F>
+// (src/dst then address g blocks).  HELD = false is the instantiation for
+// lattices with neither solid cells nor an inflow plane: the held-value
+// selection and the bounce-back test compile away (the 16-bit forms are
+// issue-bound, so those instructions cost time there).
+template <int ST, class TC, bool DO_F, bool HELD>
 __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
                                                 const typename Codec<ST, TC>::elem *__restrict__ src,
                                                 typename Codec<ST, TC>::elem *__restrict__ dst,
-                                                const typename Codec<ST, TC>::elem *__restrict__ in_eq,
+                                                const HeldEq<typename Codec<ST, TC>::elem> in_eq,
                                                 unsigned long long *__restrict__ counters) {
   using Cd = Codec<ST, TC>;
   using T = typename Cd::calc;
   using El = typename Cd::elem;
   const Cell c = decode_cell(g);
   if (!c.active) return;
-  const uint8_t cls = ph.cls ? ph.cls[c.idx] : (uint8_t)0;
-  if (cls & CLS_SOLID) return;
+  const uint8_t cls = (HELD && ph.cls) ? ph.cls[c.idx] : (uint8_t)0;
+  // Solid cells keep their (zero) entries and inflow-plane cells the inflow
+  // equilibrium; both still run the common path (their pulls stay in the
+  // domain) so that every lane joins the same full-wavefront stores, with the
+  // held value selected per lane.
+  const bool solid = HELD && (cls & CLS_SOLID);
+  const bool held = HELD && (solid || is_inflow(g, c.x, c.y, c.z));
   const size_t qs = (size_t)g.qs;
   const El *__restrict__ gs = DO_F ? src + Q * qs : src;
   El *__restrict__ gd = DO_F ? dst + Q * qs : dst;
-  if (is_inflow(g, c.x, c.y, c.z)) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      gd[q * qs + c.idx] = in_eq[Q + q];
-      if (DO_F) dst[q * qs + c.idx] = in_eq[q];
-    }
-    return;
-  }
   // All 38 pulls are issued before any arithmetic (both populations in
   // flight per wave); g then f are relaxed and streamed out.
-  const bool near = cls & CLS_NEAR;
+  const bool near = HELD && (cls & CLS_NEAR);
   T pg[Q], pf[Q];
   if (DO_F)
-    gather2<Cd>(g, ph, c, near, gs, src, qs, pg, pf);
+    gather2<Cd>(g, ph, c, near, gs, src, pg, pf);
   else
-    gather<Cd>(g, ph, c, near, gs, qs, pg);
+    gather<Cd>(g, ph, c, near, gs, pg);
   T sE = (T)0, sx, sy, sz;
 #pragma unroll
   for (int q = 0; q < Q; ++q) sE += pg[q];
@@ -445,10 +459,13 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
                         ph.c * (double)sz);
   EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
   const T om = (T)ph.omega[c.b];
+  const El zero = Cd::enc((T)0);
 #pragma unroll
-  for (int q = 0; q < Q; ++q)
-    stream_store(&gd[q * qs + c.idx], Cd::enc(pg[q] + om * (geq_dev(k, q) - pg[q])));
-  count_lanes(iv.bad, counters, 0);
+  for (int q = 0; q < Q; ++q) {
+    const El v = Cd::enc(pg[q] + om * (geq_dev(k, q) - pg[q]));
+    stream_store(&gd[at(q, c.idx)], held ? (solid ? zero : in_eq.v[Q + q]) : v);
+  }
+  count_lanes(iv.bad && !held, counters, 0);
   if (DO_F) {
     T sN = (T)0;
 #pragma unroll
@@ -457,13 +474,15 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
     k.N = (T)N;
     k.Nd = (T)(N - ph.n_ref);
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-      stream_store(&dst[q * qs + c.idx], Cd::enc(pf[q] + om * (feq_dev(k, q) - pf[q])));
+    for (int q = 0; q < Q; ++q) {
+      const El v = Cd::enc(pf[q] + om * (feq_dev(k, q) - pf[q]));
+      stream_store(&dst[at(q, c.idx)], held ? (solid ? zero : in_eq.v[q]) : v);
+    }
     // f^eq_i >= 0 needs 1 + 3 b_i > 0 for every i; the largest |b_i| is on a
     // diagonal: |b_x| + |b_y|, |b_x| + |b_z| or |b_y| + |b_z|.
     const double ax = fabs(iv.bx), ay = fabs(iv.by), az = fabs(iv.bz);
     const double mb = fmax(ax + ay, fmax(ax + az, ay + az)) * ph.inv_c;
-    count_lanes(!(3.0 * mb < 1.0), counters, 1);
+    count_lanes(!(3.0 * mb < 1.0) && !held, counters, 1);
   }
 }
 
@@ -486,15 +505,20 @@ __global__ __launch_bounds__(BLOCK) void k_init(const Geom g, const Phys ph,
   const size_t cells = (size_t)g.batch * g.per;
   if (solid_at(ph, c.idx)) {
 #pragma unroll
-    for (int q = 0; q < 2 * Q; ++q) {
-      pa[q * qs + c.idx] = Cd::enc((T)0);
-      pb[q * qs + c.idx] = Cd::enc((T)0);
+    for (int q = 0; q < Q; ++q) {
+      pa[at(q, c.idx)] = Cd::enc((T)0);
+      pb[at(q, c.idx)] = Cd::enc((T)0);
+      pa[Q * qs + at(q, c.idx)] = Cd::enc((T)0);
+      pb[Q * qs + at(q, c.idx)] = Cd::enc((T)0);
     }
     return;
   }
   if (is_inflow(g, c.x, c.y, c.z)) {
 #pragma unroll
-    for (int q = 0; q < 2 * Q; ++q) pa[q * qs + c.idx] = in_eq[q];
+    for (int q = 0; q < Q; ++q) {
+      pa[at(q, c.idx)] = in_eq[q];
+      pa[Q * qs + at(q, c.idx)] = in_eq[Q + q];
+    }
     return;
   }
   const double bx = beta0[c.idx], by = beta0[cells + c.idx], bz = beta0[2 * cells + c.idx];
@@ -504,8 +528,8 @@ __global__ __launch_bounds__(BLOCK) void k_init(const Geom g, const Phys ph,
   const EqCoef<T> k = eq_coef<T>(ph, N, e, (4.0 / 3.0) * e * g2, bx, by, bz);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    pa[q * qs + c.idx] = Cd::enc(feq_dev(k, q));
-    pa[(Q + q) * qs + c.idx] = Cd::enc(geq_dev(k, q));
+    pa[at(q, c.idx)] = Cd::enc(feq_dev(k, q));
+    pa[Q * qs + at(q, c.idx)] = Cd::enc(geq_dev(k, q));
   }
 }
 
@@ -536,7 +560,6 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const Geom g, const Phys ph,
                                                    double *__restrict__ part) {
   using Cd = Codec<ST, TC>;
   const Cell c = decode_cell(g);
-  const size_t qs = (size_t)g.qs;
   const size_t cells = (size_t)g.batch * g.per;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (c.active) {
@@ -548,8 +571,8 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const Geom g, const Phys ph,
       double N = 0.0, Eg = 0.0, sx, sy, sz, gv[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        if (Sf) N += (double)Cd::dec(Sf[q * qs + c.idx]);
-        gv[q] = (double)Cd::dec(Sg[q * qs + c.idx]);
+        if (Sf) N += (double)Cd::dec(Sf[at(q, c.idx)]);
+        gv[q] = (double)Cd::dec(Sg[at(q, c.idx)]);
         Eg += gv[q];
       }
       mirror_sums(gv, sx, sy, sz);
@@ -826,18 +849,17 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
     int accum) {
   using Cd = Codec<ST, TC>;
   const Cell c = decode_cell(g);
-  const size_t qs = (size_t)g.qs;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (c.active && adjoint_plain(g, ph, c)) {
     double pre[Q], lam[Q];
     const FaceCorr fc = face_corr(g, c);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) pre[q] = (double)Cd::dec(S[q * qs + src_fast(g, c, fc, q)]);
+    for (int q = 0; q < Q; ++q) pre[q] = (double)Cd::dec(S[at(q, src_fast(g, c, fc, q))]);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) lam[q] = lam_next[q * qs + c.idx];
+    for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, c.idx)];
     const LocalAdjoint a = adjoint_local(ph, ph.omega[c.b], pre, lam);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) lam_out[q * qs + src_fast(g, c, fc, q)] = adjoint_mu(a, lam[q], q);
+    for (int q = 0; q < Q; ++q) lam_out[at(q, src_fast(g, c, fc, q))] = adjoint_mu(a, lam[q], q);
     acc[0] = a.dtau;
   }
   double out[5];
@@ -862,7 +884,6 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_general(
     LamT *__restrict__ lam_out, LamT *__restrict__ scratch, double *__restrict__ part,
     const InflowState in, int accum) {
   using Cd = Codec<ST, TC>;
-  const size_t qs = (size_t)g.qs;
   const int li = list[(size_t)blockIdx.x * BLOCK + threadIdx.x];
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (li >= 0) {
@@ -870,11 +891,11 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_general(
     const bool solid = solid_at(ph, c.idx);
     const bool inflow = !solid && is_inflow(g, c.x, c.y, c.z);
     for (int p = 0; p < Q; ++p)
-      if (solid || !covered(g, ph, c, p, inflow)) lam_out[p * qs + c.idx] = 0.0;
+      if (solid || !covered(g, ph, c, p, inflow)) lam_out[at(p, c.idx)] = 0.0;
     if (inflow) {
       double lam[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) lam[q] = lam_next[q * qs + c.idx];
+      for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, c.idx)];
       const double g2 = 1.0 / (1.0 - (in.bx * in.bx + in.by * in.by + in.bz * in.bz));
       const double W = (4.0 / 3.0) * in.e * g2;
       const EqCoef<double> k = eq_coef<double>(ph, 0.0, in.e, W, in.bx, in.by, in.bz);
@@ -887,21 +908,21 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_general(
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const Pull p = pull_general(g, ph, c, q);
-        pre[q] = (double)Cd::dec(S[p.q * qs + p.idx]);
+        pre[q] = (double)Cd::dec(S[at(p.q, p.idx)]);
       }
 #pragma unroll
-      for (int q = 0; q < Q; ++q) lam[q] = lam_next[q * qs + c.idx];
+      for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, c.idx)];
       const LocalAdjoint a = adjoint_local(ph, ph.omega[c.b], pre, lam);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const double mu = adjoint_mu(a, lam[q], q);
         const Pull p = pull_general(g, ph, c, q);
         if (p.bounce)
-          lam_out[OPP[q] * qs + c.idx] = mu;
+          lam_out[at(OPP[q], c.idx)] = mu;
         else if (p.clamped)
-          scratch[q * qs + c.idx] = mu;
+          scratch[at(q, c.idx)] = mu;
         else
-          lam_out[q * qs + p.idx] = mu;
+          lam_out[at(q, p.idx)] = mu;
       }
       acc[0] = a.dtau;
     }
@@ -956,7 +977,6 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_faces(const Geom g, const Phy
   }
   const long long yi = cell_index(g, b, co[0], co[1], co[2]);
   if (solid_at(ph, yi)) return;
-  const size_t qs = (size_t)g.qs;
   for (int p = 1; p < Q; ++p) {
     const int e[3] = {EX[p], EY[p], EZ[p]};
     int nrm[3];
@@ -997,10 +1017,10 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_faces(const Geom g, const Phy
       if (!ok) continue;
       const long long ri = cell_index(g, b, rc[0], rc[1], rc[2]);
       if (solid_at(ph, ri) || is_inflow(g, rc[0], rc[1], rc[2])) continue;
-      acc += scratch[p * qs + ri];
+      acc += scratch[at(p, ri)];
       any = true;
     }
-    if (any) lam_out[p * qs + yi] += acc;
+    if (any) lam_out[at(p, yi)] += acc;
   }
 }
 
@@ -1014,17 +1034,16 @@ __global__ __launch_bounds__(BLOCK) void k_moments_adjoint(
   using Lm = typename Cd::lam;
   const Cell c = decode_cell(g);
   if (!c.active) return;
-  const size_t qs = (size_t)g.qs;
   const size_t cells = (size_t)g.batch * g.per;
   if (solid_at(ph, c.idx)) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) lam[q * qs + c.idx] = (Lm)0;
+    for (int q = 0; q < Q; ++q) lam[at(q, c.idx)] = (Lm)0;
     return;
   }
   double sE = 0.0, sx, sy, sz, gv[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    gv[q] = (double)Cd::dec(S[q * qs + c.idx]);
+    gv[q] = (double)Cd::dec(S[at(q, c.idx)]);
     sE += gv[q];
   }
   mirror_sums(gv, sx, sy, sz);
@@ -1034,7 +1053,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments_adjoint(
   const double ax = ph.c * gm.gx, ay = ph.c * gm.gy, az = ph.c * gm.gz;
 #pragma unroll
   for (int q = 0; q < Q; ++q)
-    lam[q * qs + c.idx] = (Lm)(gm.gE + EX[q] * ax + EY[q] * ay + EZ[q] * az);
+    lam[at(q, c.idx)] = (Lm)(gm.gE + EX[q] * ax + EY[q] * ay + EZ[q] * az);
 }
 
 // lambda_0 -> dL/de0, dL/dbeta0 (overwritten) and inflow partials.
@@ -1046,7 +1065,6 @@ __global__ __launch_bounds__(BLOCK) void k_init_adjoint(
   using Cd = Codec<ST, TC>;
   using T = double;  // reverse-mode arithmetic is FP64 for every storage
   const Cell c = decode_cell(g);
-  const size_t qs = (size_t)g.qs;
   const size_t cells = (size_t)g.batch * g.per;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (c.active) {
@@ -1056,7 +1074,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_adjoint(
       const bool inflow = is_inflow(g, c.x, c.y, c.z);
       T lam[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) lam[q] = (T)lam0[q * qs + c.idx];
+      for (int q = 0; q < Q; ++q) lam[q] = (T)lam0[at(q, c.idx)];
       const double e = inflow ? in.e : e0[c.idx];
       const double bx = inflow ? in.bx : beta0[c.idx];
       const double by = inflow ? in.by : beta0[cells + c.idx];

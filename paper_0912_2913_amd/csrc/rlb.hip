@@ -27,6 +27,7 @@ struct rlb_solver {
   double *d_omega;
   uint8_t *d_cls;
   void *d_in_eq;
+  unsigned char in_eq_host[2 * Q * 8];  // the same values, read back once at init
   unsigned long long *d_counters;
   double *d_part;      // per-workgroup partials of moments / init-adjoint reductions
   double *d_part_rev;  // reverse-step partials of the streaming kernel (accumulated)
@@ -40,6 +41,7 @@ struct rlb_solver {
   int n_gblk;
   bool glist_ready;
   bool rev_pending;  // reverse-step partials accumulated and not yet reduced
+  bool held;         // solid cells or an inflow plane exist (held cells)
 };
 
 namespace {
@@ -207,13 +209,27 @@ rlb_status launch_init(rlb_solver *h, const double *n0, const double *e0, const 
   return RLB_OK;
 }
 
+template <class El>
+HeldEq<El> held_eq(const rlb_solver *h) {
+  HeldEq<El> v;
+  static_assert(sizeof(v.v) <= sizeof(h->in_eq_host), "held values exceed the host copy");
+  std::memcpy(v.v, h->in_eq_host, sizeof(v.v));
+  return v;
+}
+
 template <int ST, class TC>
 rlb_status launch_steps(rlb_solver *h, int nsteps) {
   using El = typename Codec<ST, TC>::elem;
+  const HeldEq<El> in_eq = held_eq<El>(h);
   for (int s = 0; s < nsteps; ++s) {
-    hipLaunchKernelGGL((k_step<ST, TC, true>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
-                       h->ph, (const El *)h->pop[h->cur], (El *)h->pop[1 - h->cur],
-                       (const El *)h->d_in_eq, h->d_counters);
+    if (h->held)
+      hipLaunchKernelGGL((k_step<ST, TC, true, true>), dim3(grid_blocks(h)), dim3(BLOCK), 0,
+                         h->stream, h->g, h->ph, (const El *)h->pop[h->cur],
+                         (El *)h->pop[1 - h->cur], in_eq, h->d_counters);
+    else
+      hipLaunchKernelGGL((k_step<ST, TC, true, false>), dim3(grid_blocks(h)), dim3(BLOCK), 0,
+                         h->stream, h->g, h->ph, (const El *)h->pop[h->cur],
+                         (El *)h->pop[1 - h->cur], in_eq, h->d_counters);
     h->cur = 1 - h->cur;
   }
   RLB_HIP(hipGetLastError());
@@ -223,8 +239,14 @@ rlb_status launch_steps(rlb_solver *h, int nsteps) {
 template <int ST, class TC>
 rlb_status launch_step_g(rlb_solver *h, const void *src, void *dst) {
   using El = typename Codec<ST, TC>::elem;
-  hipLaunchKernelGGL((k_step<ST, TC, false>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
-                     h->ph, (const El *)src, (El *)dst, (const El *)h->d_in_eq, h->d_counters);
+  if (h->held)
+    hipLaunchKernelGGL((k_step<ST, TC, false, true>), dim3(grid_blocks(h)), dim3(BLOCK), 0,
+                       h->stream, h->g, h->ph, (const El *)src, (El *)dst, held_eq<El>(h),
+                       h->d_counters);
+  else
+    hipLaunchKernelGGL((k_step<ST, TC, false, false>), dim3(grid_blocks(h)), dim3(BLOCK), 0,
+                       h->stream, h->g, h->ph, (const El *)src, (El *)dst, held_eq<El>(h),
+                       h->d_counters);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -497,10 +519,14 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
     ph.cls = h->d_cls;
   }
   ph.omega = h->d_omega;
+  h->held = solid != nullptr || h->g.any_inflow != 0;
   auto launch = [&]() -> rlb_status { RLB_DISPATCH(h, launch_init, h, n0, e0, beta0); };
   s = launch();
   if (s == RLB_OK && (e = hipStreamSynchronize(h->stream)) != hipSuccess)
     s = fail(RLB_EDEVICE, std::string("rlb_init: ") + hipGetErrorString(e));
+  if (s == RLB_OK && (e = hipMemcpy(h->in_eq_host, h->d_in_eq, 2 * Q * h->elem,
+                                    hipMemcpyDeviceToHost)) != hipSuccess)
+    s = fail(RLB_EDEVICE, std::string("rlb_init: read inflow state: ") + hipGetErrorString(e));
   if (s != RLB_OK) {
     free_solver(h);
     return s;

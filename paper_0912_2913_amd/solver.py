@@ -19,6 +19,7 @@ STORAGE_DTYPE = {
     _lib.BF16DEV: torch.bfloat16,
 }
 Q = 19
+BRICK = 64  # cells per brick of the population layout
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -41,6 +42,23 @@ def make_params(nx, ny, nz, batch=1, c_l=1.0, bc=((0, 0), (0, 0), (0, 0)),
     p.n_ref, p.e_ref = float(n_ref), float(e_ref)
     p.collide = int(collide)
     return p
+
+
+def unpack_block(t: torch.Tensor, cells: int) -> torch.Tensor:
+    """Population block(s) [..., bricks, 19, 64] -> [..., 19, cells] (a copy)."""
+    lead = t.shape[:-3]
+    u = t.movedim(-2, -3).reshape(*lead, Q, t.shape[-3] * BRICK)
+    return u[..., :cells].clone()
+
+
+def pack_block(a, nbrick: int, cells: int, dtype, device, fill: float = 0.0) -> torch.Tensor:
+    """[..., 19, cells] -> population block(s) [..., bricks, 19, 64] (element
+    (q, cell) at (cell // 64) * 19 * 64 + q * 64 + cell % 64); padding = fill."""
+    a = torch.as_tensor(a)
+    lead = a.shape[:-2]
+    full = torch.full((*lead, Q, nbrick * BRICK), fill, dtype=dtype, device=device)
+    full[..., :cells] = a.to(device, dtype)
+    return full.reshape(*lead, Q, nbrick, BRICK).movedim(-3, -2).contiguous()
 
 
 def buffer_layout(p: _lib.Params) -> Tuple[int, int]:
@@ -72,9 +90,10 @@ class Solver:
         self.dtype = STORAGE_DTYPE[self.storage]
         self.lam_dtype = torch.float64  # adjoint buffers are FP64 for every storage
         self.q_stride, self.state_bytes = buffer_layout(self.params)
+        self.nbrick = self.q_stride // BRICK
         with torch.cuda.stream(self.stream):
-            self.pop = [torch.empty((2, Q, self.q_stride), dtype=self.dtype, device=self.device)
-                        for _ in range(2)]
+            self.pop = [torch.empty((2, self.nbrick, Q, BRICK), dtype=self.dtype,
+                                    device=self.device) for _ in range(2)]
             f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(self.device)
             n0 = f64(np.asarray(s.n0).reshape(-1))
             e0 = f64(np.asarray(s.e0).reshape(-1))
@@ -107,12 +126,13 @@ class Solver:
               "rlb_advance_g")
 
     def new_g_seq(self, n: int) -> torch.Tensor:
-        """n contiguous g blocks, [n][19][q_stride]."""
-        return torch.empty((n, Q, self.q_stride), dtype=self.dtype, device=self.device)
+        """n contiguous g blocks, [n][bricks][19][64]."""
+        return torch.empty((n, self.nbrick, Q, BRICK), dtype=self.dtype, device=self.device)
 
     def _seq_stride(self, g_seq: torch.Tensor) -> int:
-        if g_seq.dim() != 3 or g_seq.shape[1:] != (Q, self.q_stride) or not g_seq.is_contiguous():
-            raise ValueError("g_seq must be a contiguous [n][19][q_stride] tensor")
+        if g_seq.dim() != 4 or tuple(g_seq.shape[1:]) != (self.nbrick, Q, BRICK) \
+                or not g_seq.is_contiguous():
+            raise ValueError("g_seq must be a contiguous [n][bricks][19][64] tensor")
         if g_seq.dtype != self.dtype:
             raise ValueError("g_seq dtype does not match the storage format")
         return Q * self.q_stride * g_seq.element_size()
@@ -142,7 +162,8 @@ class Solver:
               "rlb_adjoint_flush")
 
     def state(self) -> torch.Tensor:
-        """The buffer holding the current state, [2][19][q_stride] (a view, not a copy)."""
+        """The buffer holding the current state, [2][bricks][19][64] (the buffer itself,
+        not a copy; see unpack)."""
         p = ctypes.c_void_p()
         check(_lib.lib().rlb_current(self.h, ctypes.byref(p)), "rlb_current")
         for t in self.pop:
@@ -154,10 +175,25 @@ class Solver:
         return self.state()[1]
 
     def new_g(self) -> torch.Tensor:
-        return torch.empty((Q, self.q_stride), dtype=self.dtype, device=self.device)
+        """A g block, [bricks][19][64] in the storage format."""
+        return torch.empty((self.nbrick, Q, BRICK), dtype=self.dtype, device=self.device)
 
     def new_lam(self) -> torch.Tensor:
-        return torch.empty((Q, self.q_stride), dtype=self.lam_dtype, device=self.device)
+        """An adjoint buffer, [bricks][19][64] float64."""
+        return torch.empty((self.nbrick, Q, BRICK), dtype=self.lam_dtype, device=self.device)
+
+    # Layout conversion for host-side inspection and test I/O (no arithmetic):
+    # a population block stores bricks of 64 cells with their 19 directions
+    # one after another; unpack gives the plain [19][cells] view of the values.
+    def unpack(self, t: torch.Tensor) -> torch.Tensor:
+        """[..., bricks, 19, 64] -> [..., 19, cells] (a copy)."""
+        return unpack_block(t, self.cells)
+
+    def pack(self, a, dtype=None, fill: float = 0.0) -> torch.Tensor:
+        """[..., 19, cells] (array or tensor) -> [..., bricks, 19, 64]; padding
+        cells hold ``fill``."""
+        return pack_block(a, self.nbrick, self.cells, self.dtype if dtype is None else dtype,
+                          self.device, fill)
 
     def moments(self, sums: bool = False):
         """(n, e, beta[3]) device float64 tensors of shape [cells] / [3, cells];

@@ -120,3 +120,24 @@ def test_null_handle_is_rejected(L):
     assert lib.rlb_adjoint_sweep(None, None, 0, 1, None, None, None) == L.RLB_EINVAL
     assert lib.rlb_adjoint_flush(None, None, None, None) == L.RLB_EINVAL
     assert lib.rlb_destroy(None) == L.RLB_OK
+
+
+def test_brick_layout_pack_unpack_follow_the_documented_formula():
+    """Element (q, cell) of a population block sits at
+    (cell // 64) * 19 * 64 + q * 64 + cell % 64 (the layout rlb.h documents)."""
+    import torch
+
+    from paper_0912_2913_amd.solver import pack_block, unpack_block
+
+    for cells in (1, 63, 64, 150, 1000):
+        nb = (cells + 63) // 64
+        a = torch.arange(19 * cells, dtype=torch.float64).reshape(19, cells) + 1.0
+        t = pack_block(a, nb, cells, torch.float64, "cpu", fill=-1.0)
+        assert tuple(t.shape) == (nb, 19, 64)
+        flat = t.reshape(-1).numpy()
+        q, c = np.meshgrid(np.arange(19), np.arange(cells), indexing="ij")
+        assert np.array_equal(flat[(c // 64) * 19 * 64 + q * 64 + c % 64], a.numpy())
+        assert (flat == -1.0).sum() == 19 * (nb * 64 - cells)
+        assert torch.equal(unpack_block(t, cells), a)
+        two = torch.stack([a, 2 * a])
+        assert torch.equal(unpack_block(pack_block(two, nb, cells, torch.float64, "cpu"), cells), two)

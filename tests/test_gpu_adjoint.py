@@ -38,15 +38,11 @@ def setups():
 
 
 def upload_g(sv, g: np.ndarray) -> torch.Tensor:
-    t = torch.zeros((19, sv.q_stride), dtype=sv.dtype, device=sv.device)
-    t[:, : sv.cells] = torch.as_tensor(g)
-    return t
+    return sv.pack(g)
 
 
 def upload_lam(sv, lam: np.ndarray) -> torch.Tensor:
-    t = torch.full((19, sv.q_stride), float("nan"), dtype=sv.lam_dtype, device=sv.device)
-    t[:, : sv.cells] = torch.as_tensor(lam)
-    return t
+    return sv.pack(lam, dtype=sv.lam_dtype, fill=float("nan"))
 
 
 def rel(a, b):
@@ -73,7 +69,7 @@ def test_adjoint_step_matches_oracle(name):
     db = torch.zeros(3, dtype=torch.float64, device=sv.device)
     de = torch.zeros(1, dtype=torch.float64, device=sv.device)
     sv.adjoint_step(g, ln, lo, dt, db, de)
-    got = lo[:, : sv.cells].cpu().numpy()
+    got = sv.unpack(lo).cpu().numpy()
     assert np.isfinite(got).all(), "some lambda_t entry was never written"
     assert rel(got, lam_t) <= 1e-12
     assert rel(dt.cpu().numpy(), dtau) <= 1e-12
@@ -81,7 +77,7 @@ def test_adjoint_step_matches_oracle(name):
         assert rel(db.cpu().numpy(), dbin) <= 1e-12
         assert rel(de.cpu().numpy(), np.array([dein])) <= 1e-12
     # lam_next is left unmodified
-    assert np.array_equal(ln[:, : sv.cells].cpu().numpy(), lam)
+    assert np.array_equal(sv.unpack(ln).cpu().numpy(), lam)
     sv.close()
 
 
@@ -99,10 +95,10 @@ def test_moments_and_init_adjoint_match_oracle(name):
     dLdb = rng.standard_normal((3, s.cells))
     lam_ref = oracle.moments_adjoint(p, Sg, dLde, dLdb)
     sv = Solver(s)
-    lam = torch.empty((19, sv.q_stride), dtype=sv.lam_dtype, device=sv.device)
+    lam = sv.new_lam()
     sv.moments_adjoint(upload_g(sv, Sg), torch.as_tensor(dLde, device=sv.device),
                        torch.as_tensor(dLdb, device=sv.device), lam)
-    assert rel(lam[:, : sv.cells].cpu().numpy(), lam_ref) <= 1e-12
+    assert rel(sv.unpack(lam).cpu().numpy(), lam_ref) <= 1e-12
     lam0 = rng.standard_normal((19, s.cells))
     de0_ref, db0_ref, dbin_ref, dein_ref = oracle.init_adjoint(p, s.e0, s.beta0, lam0)
     de0 = torch.empty(s.cells, dtype=torch.float64, device=sv.device)
@@ -236,14 +232,14 @@ def test_advance_and_trajectory_equal_step_g_chain_bitwise(storage):
     for n in (0, 1, 2, 5, 6):
         dst = sv.new_g().fill_(7)
         sv.advance_g(g0, dst, tmp, n)
-        assert torch.equal(bits(dst[:, : sv.cells][:, fl]), bits(chain[n][:, : sv.cells][:, fl])), n
+        assert torch.equal(bits(sv.unpack(dst)[:, fl]), bits(sv.unpack(chain[n])[:, fl])), n
     assert torch.equal(bits(g0), bits(chain[0]))  # the source is read only
     seq = sv.new_g_seq(7)
     seq[0].copy_(g0)
     seq[1:].fill_(3)
     sv.trajectory_g(seq, 5)
     for j in range(5):
-        assert torch.equal(bits(seq[j, :, : sv.cells][:, fl]), bits(chain[j][:, : sv.cells][:, fl])), j
+        assert torch.equal(bits(sv.unpack(seq[j])[:, fl]), bits(sv.unpack(chain[j])[:, fl])), j
     assert bool((seq[5:] == 3).all())  # blocks beyond n untouched
     sv.close()
 
@@ -276,7 +272,7 @@ def test_adjoint_sweep_equals_pending_adjoint_steps(name):
     for j in range(n - 1, -1, -1):
         sv.adjoint_step(seq[j], a, b, *(g_pe if j == 0 else (None, None, None)))
         a, b = b, a
-    assert torch.equal(a[:, : sv.cells], res[:, : sv.cells])
+    assert torch.equal(sv.unpack(a), sv.unpack(res))
     for x, y in zip(g_sw, g_pe):
         assert torch.equal(x, y)
 
