@@ -64,22 +64,25 @@ def lib():
     L.ora_collide.restype = ctypes.c_int
     common = [_ip, ctypes.c_double, _ip, _dp, _u8p]
     L.ora_init.argtypes = common + [_dp, _dp, _dp, _dp]
-    L.ora_run.argtypes = common + [_dp, _dp, ctypes.c_int]
+    rxp = ctypes.POINTER(Relax)
+    L.ora_run.argtypes = common + [rxp, _dp, ctypes.c_int]
     L.ora_run.restype = ctypes.c_long
-    L.ora_run_g.argtypes = common + [_dp, _dp, ctypes.c_int]
+    L.ora_run_g.argtypes = common + [rxp, _dp, ctypes.c_int]
     L.ora_run_g.restype = ctypes.c_long
-    L.ora_update_cells.argtypes = common + [_dp, _dp, ctypes.c_long, _lp, _dp]
+    L.ora_update_cells.argtypes = common + [rxp, _dp, ctypes.c_long, _lp, _dp]
     L.ora_moments.argtypes = [_ip, ctypes.c_double, _u8p, _dp, _dp, _dp, _dp, _dp]
-    L.ora_adjoint_step.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.ora_adjoint_step.argtypes = common + [rxp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.ora_adjoint_step.restype = ctypes.c_int
+    L.ora_transport.argtypes = [_ip, ctypes.c_double, _u8p, _dp, rxp, _dp, _dp, _dp, _dp]
     L.ora_moments_adjoint.argtypes = [_ip, ctypes.c_double, _u8p, _dp, _dp, _dp, _dp]
     L.ora_init_adjoint.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
-    L.ora_loss.argtypes = common + [_dp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp]
+    L.ora_loss.argtypes = common + [rxp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp]
     L.ora_loss.restype = ctypes.c_double
-    L.ora_loss_cs.argtypes = common + [_dp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp,
-                                       _dp, _dp, _dp, _dp, _dp]
+    L.ora_loss_cs.argtypes = common + [rxp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp,
+                                       _dp, _dp, _dp, _dp, _dp, _dp]
     L.ora_loss_cs.restype = ctypes.c_double
-    L.ora_gradient.argtypes = common + [_dp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp,
-                                        _dp, _dp, _dp, _dp]
+    L.ora_gradient.argtypes = common + [rxp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp,
+                                        _dp, _dp, _dp, _dp, _dp]
     L.ora_gradient.restype = ctypes.c_double
     _lib = L
     return L
@@ -98,6 +101,13 @@ def _f64(a) -> Optional[np.ndarray]:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+class Relax(ctypes.Structure):
+    """Relaxation source of a run (mirrors the oracle's OraRelax)."""
+
+    _fields_ = [("tau", _dp), ("tau_cell", _dp), ("eta_s", ctypes.c_double),
+                ("d_G", ctypes.c_double)]
+
+
 @dataclass
 class Problem:
     """A lattice problem in the oracle's terms (all host data, FP64)."""
@@ -111,6 +121,9 @@ class Problem:
     inflow: Sequence[float] = (1.0, 1.0, 0.0, 0.0, 0.0)  # n, e, beta_x, beta_y, beta_z
     tau: Sequence[float] = (0.6,)
     solid: Optional[np.ndarray] = None  # uint8 [cells]
+    tau_cell: Optional[np.ndarray] = None  # [cells]: per-cell relaxation times
+    eta_s: float = 0.0  # > 0: hold eta/s fixed (tau from the local state, f+g runs)
+    d_G: float = 16.0  # degeneracy in n_eq = d_G T^3 / pi^2
 
     @property
     def cells(self) -> int:
@@ -128,10 +141,16 @@ class Problem:
         if tau.size == 1 and self.batch > 1:
             tau = np.full(self.batch, tau[0])
         assert tau.size == self.batch
-        self._keep = (dims, bc, inflow, solid, tau)
+        tc = None
+        if self.tau_cell is not None:
+            tc = np.ascontiguousarray(np.asarray(self.tau_cell, dtype=np.float64).reshape(-1))
+            assert tc.size == self.cells
+        rx = Relax(tau.ctypes.data_as(_dp), tc.ctypes.data_as(_dp) if tc is not None else None,
+                   float(self.eta_s), float(self.d_G))
+        self._keep = (dims, bc, inflow, solid, tau, tc, rx)
         return (dims.ctypes.data_as(_ip), ctypes.c_double(self.c_l), bc.ctypes.data_as(_ip),
                 inflow.ctypes.data_as(_dp),
-                solid.ctypes.data_as(_u8p) if solid is not None else None), tau
+                solid.ctypes.data_as(_u8p) if solid is not None else None), ctypes.byref(rx)
 
 
 def lattice():
@@ -177,23 +196,25 @@ def init(p: Problem, n0, e0, beta0) -> np.ndarray:
 
 def run(p: Problem, S: np.ndarray, nsteps: int) -> int:
     """Advance S ([2][19][cells], in place) by nsteps; returns the unphysical-update count."""
-    args, tau = p._args()
+    args, rx = p._args()
     assert S.shape == (2, Q, p.cells) and S.dtype == np.float64 and S.flags.c_contiguous
-    return int(lib().ora_run(*args, _d(tau), _d(S), int(nsteps)))
+    return int(lib().ora_run(*args, rx, _d(S), int(nsteps)))
 
 
 def run_g(p: Problem, Sg: np.ndarray, nsteps: int) -> int:
-    args, tau = p._args()
+    if p.eta_s > 0:
+        raise ValueError("holding eta/s needs the f population: use run()")
+    args, rx = p._args()
     assert Sg.shape == (Q, p.cells) and Sg.flags.c_contiguous
-    return int(lib().ora_run_g(*args, _d(tau), _d(Sg), int(nsteps)))
+    return int(lib().ora_run_g(*args, rx, _d(Sg), int(nsteps)))
 
 
 def update_cells(p: Problem, S: np.ndarray, idx) -> np.ndarray:
     """One step evaluated at the given linear cell indices: returns [k][38] (f then g)."""
-    args, tau = p._args()
+    args, rx = p._args()
     idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
     out = np.zeros((idx.size, 2 * Q))
-    lib().ora_update_cells(*args, _d(tau), _d(S), ctypes.c_long(idx.size),
+    lib().ora_update_cells(*args, rx, _d(S), ctypes.c_long(idx.size),
                            idx.ctypes.data_as(_lp), _d(out))
     return out
 
@@ -212,16 +233,22 @@ def moments(p: Problem, S: np.ndarray):
     return n, e, b, sums
 
 
-def adjoint_step(p: Problem, Sg, lam_next):
-    """One g-only reverse step; returns (lam_t, dL/dtau[batch], dL/dbeta_in[3], dL/de_in)."""
-    args, tau = p._args()
+def adjoint_step(p: Problem, Sg, lam_next, per_cell: bool = False):
+    """One g-only reverse step; returns (lam_t, dL/dtau[batch], dL/dbeta_in[3], dL/de_in)
+    and, with per_cell, also dL/dtau(x)[cells] (the per-cell relaxation times)."""
+    if p.eta_s > 0:
+        raise ValueError("the g-only reverse step does not hold while eta/s is held")
+    args, rx = p._args()
     Sg, lam_next = _f64(Sg), _f64(lam_next)
     lam_out = np.zeros((Q, p.cells))
     dtau = np.zeros(p.batch)
     dbin = np.zeros(3)
     dein = np.zeros(1)
-    lib().ora_adjoint_step(*args, _d(tau), _d(Sg), _d(lam_next), _d(lam_out), _d(dtau),
-                           _d(dbin), _d(dein))
+    dcell = np.zeros(p.cells)
+    lib().ora_adjoint_step(*args, rx, _d(Sg), _d(lam_next), _d(lam_out), _d(dtau),
+                           _d(dbin), _d(dein), _d(dcell))
+    if per_cell:
+        return lam_out, dtau, dbin, dein[0], dcell
     return lam_out, dtau, dbin, dein[0]
 
 
@@ -264,21 +291,27 @@ class Loss:
 
 
 def loss(p: Problem, e0, beta0, nsteps, L: Loss) -> float:
-    args, tau = p._args()
+    if p.eta_s > 0:
+        raise ValueError("g-only runs do not hold eta/s")
+    args, rx = p._args()
     e0, beta0 = _f64(e0).reshape(-1), np.ascontiguousarray(_f64(beta0).reshape(3, -1))
-    return float(lib().ora_loss(*args, _d(tau), _d(e0), _d(beta0), int(nsteps), *L.ptrs()))
+    return float(lib().ora_loss(*args, rx, _d(e0), _d(beta0), int(nsteps), *L.ptrs()))
 
 
 def loss_cs(p: Problem, e0, beta0, nsteps, L: Loss, d_tau=None, d_inflow=None, d_e0=None,
-            d_beta0=None):
-    """Complex-step directional derivative dL.d; returns (L, dL.d)."""
-    args, tau = p._args()
+            d_beta0=None, d_tau_cell=None):
+    """Complex-step directional derivative dL.d; returns (L, dL.d).  d_tau_cell
+    perturbs the per-cell relaxation times (needs p.tau_cell)."""
+    if p.eta_s > 0:
+        raise ValueError("g-only runs do not hold eta/s")
+    assert d_tau_cell is None or p.tau_cell is not None
+    args, rx = p._args()
     e0, beta0 = _f64(e0).reshape(-1), np.ascontiguousarray(_f64(beta0).reshape(3, -1))
-    dt, di, de, db = (_f64(v).reshape(-1) if v is not None else None
-                      for v in (d_tau, d_inflow, d_e0, d_beta0))
+    dt, di, de, db, dc = (_f64(v).reshape(-1) if v is not None else None
+                          for v in (d_tau, d_inflow, d_e0, d_beta0, d_tau_cell))
     lv = np.zeros(1)
-    r = lib().ora_loss_cs(*args, _d(tau), _d(e0), _d(beta0), int(nsteps), *L.ptrs(),
-                          _d(dt), _d(di), _d(de), _d(db), _d(lv))
+    r = lib().ora_loss_cs(*args, rx, _d(e0), _d(beta0), int(nsteps), *L.ptrs(),
+                          _d(dt), _d(di), _d(de), _d(db), _d(dc), _d(lv))
     return float(lv[0]), float(r)
 
 
@@ -290,16 +323,34 @@ class Gradient:
     beta_in: np.ndarray
     e0: np.ndarray
     beta0: np.ndarray
+    tau_cell: np.ndarray  # dL/dtau(x): the gradient with respect to per-cell relaxation times
 
 
 def gradient(p: Problem, e0, beta0, nsteps, L: Loss) -> Gradient:
     """Store-all FP64 reverse sweep of a g-only run (oracle's own adjoint)."""
-    args, tau = p._args()
+    if p.eta_s > 0:
+        raise ValueError("g-only runs do not hold eta/s")
+    args, rx = p._args()
     e0, beta0 = _f64(e0).reshape(-1), np.ascontiguousarray(_f64(beta0).reshape(3, -1))
     gt = np.zeros(p.batch)
     gi = np.zeros(4)
     ge = np.zeros(p.cells)
     gb = np.zeros((3, p.cells))
-    lv = lib().ora_gradient(*args, _d(tau), _d(e0), _d(beta0), int(nsteps), *L.ptrs(),
-                            _d(gt), _d(gi), _d(ge), _d(gb))
-    return Gradient(float(lv), gt, float(gi[0]), gi[1:4].copy(), ge, gb)
+    gc = np.zeros(p.cells)
+    lv = lib().ora_gradient(*args, rx, _d(e0), _d(beta0), int(nsteps), *L.ptrs(),
+                            _d(gt), _d(gi), _d(ge), _d(gb), _d(gc))
+    return Gradient(float(lv), gt, float(gi[0]), gi[1:4].copy(), ge, gb, gc)
+
+
+def transport(p: Problem, S: np.ndarray):
+    """(T, s, eta, eta/s) per cell of a stored f+g state ([2][19][cells]), each
+    cell with its relaxation time (per instance, per-cell field, or the eta/s
+    rule at its fields); zeros on solid cells."""
+    dims = np.array([p.nx, p.ny, p.nz, p.batch], dtype=np.int32)
+    _, rx = p._args()
+    solid = None if p.solid is None else np.ascontiguousarray(p.solid.reshape(-1).astype(np.uint8))
+    out = [np.zeros(p.cells) for _ in range(4)]
+    lib().ora_transport(dims.ctypes.data_as(_ip), float(p.c_l),
+                        solid.ctypes.data_as(_u8p) if solid is not None else None, _d(S), rx,
+                        *[_d(o) for o in out])
+    return tuple(out)

@@ -23,6 +23,11 @@
 //   * ultra-relativistic equilibria: eqs. (equil1s), (equil2as), (equil2bs),
 //     written literally with gamma^2 = 1/(1 - |beta|^2) and c = 1.
 //
+//   * shear viscosity of the model, eta = (4/9) gamma^2 e (tau - dt/2) c_l^2
+//     (end of the equilibrium section), and the transport quantities of the
+//     shock-tube section: T = e / (3n), n_eq = d_G T^3 / pi^2, fugacity
+//     lambda = n / n_eq, entropy density s = 4n - n ln(lambda).
+//
 // Readings where the paper is silent (each one is listed in the design notes):
 //   * velocity ordering (Fig. 2 is missing): 0 rest; 1..6 the axis pairs
 //     (+x,-x,+y,-y,+z,-z); 7..18 the diagonal pairs (xy, xz, yz), each pair
@@ -39,6 +44,12 @@
 //     (pull from a solid source returns the cell's own opposite population).
 //     Precedence: wrap/clamp per axis, then the solid test on the resolved
 //     source.  Solid cells are never updated and hold zeros.
+//   * relaxation time: tau per instance, or a per-cell field tau(x), or (to
+//     hold eta/s fixed, as the shock-tube section characterises its runs by
+//     eta/s) tau set in every cell and step from its pre-collision moments by
+//     solving the viscosity relation for tau with eta = (eta/s) s.  Lattice
+//     units: dx = 1, dt = 1/c_l, tau in units of dt, so
+//     eta = (4/9) gamma^2 e c_l (tau - 1/2).
 
 #include <cmath>
 #include <complex>
@@ -201,6 +212,54 @@ bool collide(const T pf[Q], const T pg[Q], T tau, double c_l, bool do_f, T of[Q]
   return ok;
 }
 
+// Transport quantities of one cell from its fields (n, e, beta) and tau:
+// temperature T = e/(3n), equilibrium density n_eq = d_G T^3/pi^2, fugacity
+// lambda = n/n_eq, entropy density s = 4n - n ln(lambda), shear viscosity
+// eta = (4/9) gamma^2 e (tau - dt/2) c_l^2 with dt = 1/c_l.
+template <class T>
+void transport(T n, T eps, const T beta[3], T tau, double c_l, double d_G, T *temp, T *s, T *eta) {
+  using std::log;
+  const double pi = 3.14159265358979323846;
+  T Tm = eps / (3.0 * n);
+  T n_eq = d_G * Tm * Tm * Tm / (pi * pi);
+  T lam = n / n_eq;
+  T b2 = beta[0] * beta[0] + beta[1] * beta[1] + beta[2] * beta[2];
+  T gamma2 = 1.0 / (1.0 - b2);
+  double dt = 1.0 / c_l;
+  *temp = Tm;
+  *s = 4.0 * n - n * log(lam);
+  *eta = (4.0 / 9.0) * gamma2 * eps * (tau * dt - dt / 2.0) * (c_l * c_l);
+}
+
+// The relaxation time that gives eta/s = eta_s at the pre-collision moments
+// of one cell (both populations): the viscosity relation
+// eta = (4/9) gamma^2 e (tau dt - dt/2) c_l^2 solved for tau, with
+// eta = eta_s * s and s from the same moments.
+template <class T>
+T tau_for_eta_s(const T pf[Q], const T pg[Q], double c_l, double eta_s, double d_G) {
+  T N, E, M[3], n, eps, beta[3];
+  moment_sums(pf, pg, c_l, &N, &E, M);
+  invert(N, E, M, &n, &eps, beta);
+  T Tm, s, eta_unused;
+  transport(n, eps, beta, T(1.0), c_l, d_G, &Tm, &s, &eta_unused);
+  T b2 = beta[0] * beta[0] + beta[1] * beta[1] + beta[2] * beta[2];
+  T gamma2 = 1.0 / (1.0 - b2);
+  double dt = 1.0 / c_l;
+  T eta = eta_s * s;
+  return (eta / ((4.0 / 9.0) * gamma2 * eps * (c_l * c_l)) + dt / 2.0) / dt;
+}
+
+// Relaxation time of every update: per instance (tau[batch]), or a per-cell
+// field (tau_cell[cells]), or set from the local state to hold eta/s fixed
+// (eta_s > 0, f+g steps only).
+template <class T>
+struct Relax {
+  const T *tau;
+  const T *tau_cell;
+  double eta_s;
+  double d_G;
+};
+
 // Where the pull of direction q at cell c comes from: (source cell index,
 // source direction).  A solid resolved source means half-way bounce-back: the
 // cell's own opposite population.
@@ -221,8 +280,8 @@ Source pull_source(const Lattice &L, const uint8_t *solid, int b, const int c[3]
 // (cells = batch * nz * ny * nx, x fastest).  With do_f false only the g block
 // is read and written (the pointers then address a g block of 19*cells).
 template <class T>
-long step(const Lattice &L, const T *tau, const uint8_t *solid, const T in_f[Q], const T in_g[Q],
-          const T *Sin, T *Sout, bool do_f) {
+long step(const Lattice &L, const Relax<T> &rx, const uint8_t *solid, const T in_f[Q],
+          const T in_g[Q], const T *Sin, T *Sout, bool do_f) {
   const long C = L.cells();
   const T *fin = Sin, *gin = do_f ? Sin + (long)Q * C : Sin;
   T *fout = Sout, *gout = do_f ? Sout + (long)Q * C : Sout;
@@ -253,7 +312,9 @@ long step(const Lattice &L, const T *tau, const uint8_t *solid, const T in_f[Q],
             pg[q] = gin[(long)s.q * C + s.idx];
             pf[q] = do_f ? fin[(long)s.q * C + s.idx] : T(0.0);
           }
-          if (!collide(pf, pg, tau[b], L.c_l, do_f, of, og)) ++unphysical;
+          T tau = rx.tau_cell ? rx.tau_cell[i] : rx.tau[b];
+          if (rx.eta_s > 0.0) tau = tau_for_eta_s(pf, pg, L.c_l, rx.eta_s, rx.d_G);
+          if (!collide(pf, pg, tau, L.c_l, do_f, of, og)) ++unphysical;
           for (int q = 0; q < Q; ++q) {
             gout[(long)q * C + i] = og[q];
             if (do_f) fout[(long)q * C + i] = of[q];
@@ -403,9 +464,10 @@ void fields_jacobian(const double g[Q], double c_l, double J[4][Q]) {
 // mu_p to the stored population it pulled from.  Inflow cells (held at the
 // inflow equilibrium) route lam_{t+1} into d/d(e_in, beta_in); tau adds
 // lam . d post / d tau.
-void adjoint_step_g(const Lattice &L, const double *tau, const uint8_t *solid, double in_e,
+void adjoint_step_g(const Lattice &L, const Relax<double> &rx, const uint8_t *solid, double in_e,
                     const double in_b[3], const double *Sg, const double *lam_next,
-                    double *lam_out, double *dtau, double *dbeta_in, double *de_in) {
+                    double *lam_out, double *dtau, double *dbeta_in, double *de_in,
+                    double *dtau_cell) {
   const long C = L.cells();
   for (long k = 0; k < (long)Q * C; ++k) lam_out[k] = 0.0;
   double Jin[Q][4];
@@ -434,16 +496,17 @@ void adjoint_step_g(const Lattice &L, const double *tau, const uint8_t *solid, d
             pg[q] = Sg[(long)src[q].q * C + src[q].idx];
           }
           double J[Q][Q], dt[Q];
-          collide_jacobian(pg, tau[b], L.c_l, J, dt);
+          collide_jacobian(pg, rx.tau_cell ? rx.tau_cell[i] : rx.tau[b], L.c_l, J, dt);
           for (int p = 0; p < Q; ++p) {
             double mu = 0.0;
             for (int q = 0; q < Q; ++q) mu += lam[q] * J[q][p];
             lam_out[(long)src[p].q * C + src[p].idx] += mu;
           }
-          if (dtau) {
+          if (dtau || dtau_cell) {
             double s = 0.0;
             for (int q = 0; q < Q; ++q) s += lam[q] * dt[q];
-            dtau[b] += s;
+            if (dtau) dtau[b] += s;
+            if (dtau_cell) dtau_cell[i] += s;
           }
         }
 }
@@ -507,6 +570,8 @@ void init_adjoint_g(const Lattice &L, const uint8_t *solid, const double *e0, co
         }
 }
 
+Relax<double> relax_of(const void *r);
+
 }  // namespace
 
 // ===========================================================================
@@ -516,6 +581,15 @@ void init_adjoint_g(const Lattice &L, const uint8_t *solid, const double *e0, co
 // batch}; bc = {x_lo, x_hi, y_lo, y_hi, z_lo, z_hi} (0 periodic, 1 outflow,
 // 2 inflow); inflow = {n, e, beta_x, beta_y, beta_z}.
 extern "C" {
+
+// Relaxation source of a run: tau[batch]; optional tau_cell[cells]; eta_s > 0
+// holds eta/s fixed with degeneracy d_G (f+g runs only).
+struct OraRelax {
+  const double *tau;
+  const double *tau_cell;
+  double eta_s;
+  double d_G;
+};
 
 int ora_num_directions() { return Q; }
 
@@ -560,7 +634,8 @@ void ora_init(const int32_t *dims, double c_l, const int32_t *bc, const double *
 // Runs nsteps f+g steps in place on S (a scratch copy is allocated here).
 // Returns the number of unphysical cell updates seen.
 long ora_run(const int32_t *dims, double c_l, const int32_t *bc, const double *inflow,
-             const uint8_t *solid, const double *tau, double *S, int nsteps) {
+             const uint8_t *solid, const OraRelax *rxp, double *S, int nsteps) {
+  const Relax<double> rx = relax_of(rxp);
   Lattice L = make_lattice(dims, c_l, bc);
   double in_f[Q], in_g[Q];
   inflow_equilibria<double>(L, inflow[0], inflow[1], inflow + 2, in_f, in_g);
@@ -569,7 +644,7 @@ long ora_run(const int32_t *dims, double c_l, const int32_t *bc, const double *i
   double *a = S, *b = tmp.data();
   long bad = 0;
   for (int t = 0; t < nsteps; ++t) {
-    bad += step<double>(L, tau, solid, in_f, in_g, a, b, true);
+    bad += step<double>(L, rx, solid, in_f, in_g, a, b, true);
     std::swap(a, b);
   }
   if (a != S) std::memcpy(S, a, n * sizeof(double));
@@ -578,7 +653,9 @@ long ora_run(const int32_t *dims, double c_l, const int32_t *bc, const double *i
 
 // Same as ora_run on the g population only (S is [19][cells]).
 long ora_run_g(const int32_t *dims, double c_l, const int32_t *bc, const double *inflow,
-               const uint8_t *solid, const double *tau, double *S, int nsteps) {
+               const uint8_t *solid, const OraRelax *rxp, double *S, int nsteps) {
+  const Relax<double> rx = relax_of(rxp);
+  if (rx.eta_s > 0.0) return -1;  // holding eta/s needs n, i.e. the f population
   Lattice L = make_lattice(dims, c_l, bc);
   double in_f[Q], in_g[Q];
   inflow_equilibria<double>(L, inflow[0], inflow[1], inflow + 2, in_f, in_g);
@@ -587,7 +664,7 @@ long ora_run_g(const int32_t *dims, double c_l, const int32_t *bc, const double 
   double *a = S, *b = tmp.data();
   long bad = 0;
   for (int t = 0; t < nsteps; ++t) {
-    bad += step<double>(L, tau, solid, in_f, in_g, a, b, false);
+    bad += step<double>(L, rx, solid, in_f, in_g, a, b, false);
     std::swap(a, b);
   }
   if (a != S) std::memcpy(S, a, n * sizeof(double));
@@ -597,8 +674,9 @@ long ora_run_g(const int32_t *dims, double c_l, const int32_t *bc, const double 
 // Post-step populations of selected cells only: out[k][0..37] = (f_0..f_18,
 // g_0..g_18) of cell idx[k] after one step from S (the full stored state).
 void ora_update_cells(const int32_t *dims, double c_l, const int32_t *bc, const double *inflow,
-                      const uint8_t *solid, const double *tau, const double *S, long ncells,
+                      const uint8_t *solid, const OraRelax *rxp, const double *S, long ncells,
                       const long *idx, double *out) {
+  const Relax<double> rx = relax_of(rxp);
   Lattice L = make_lattice(dims, c_l, bc);
   double in_f[Q], in_g[Q];
   inflow_equilibria<double>(L, inflow[0], inflow[1], inflow + 2, in_f, in_g);
@@ -632,7 +710,9 @@ void ora_update_cells(const int32_t *dims, double c_l, const int32_t *bc, const 
       pf[q] = f[(long)s.q * C + s.idx];
       pg[q] = g[(long)s.q * C + s.idx];
     }
-    collide<double>(pf, pg, tau[b], L.c_l, true, o, o + Q);
+    double tau = rx.tau_cell ? rx.tau_cell[i] : rx.tau[b];
+    if (rx.eta_s > 0.0) tau = tau_for_eta_s(pf, pg, L.c_l, rx.eta_s, rx.d_G);
+    collide<double>(pf, pg, tau, L.c_l, true, o, o + Q);
   }
 }
 
@@ -666,13 +746,16 @@ void ora_moments(const int32_t *dims, double c_l, const uint8_t *solid, const do
 // g-only versions of the reverse-mode building blocks (oracle layout
 // [19][cells]); gradients are accumulated (+=) except lam_out / lam / dLde0 /
 // dLdb0 which are overwritten.
-void ora_adjoint_step(const int32_t *dims, double c_l, const int32_t *bc, const double *inflow,
-                      const uint8_t *solid, const double *tau, const double *Sg,
-                      const double *lam_next, double *lam_out, double *dtau, double *dbeta_in,
-                      double *de_in) {
+int ora_adjoint_step(const int32_t *dims, double c_l, const int32_t *bc, const double *inflow,
+                     const uint8_t *solid, const OraRelax *rxp, const double *Sg,
+                     const double *lam_next, double *lam_out, double *dtau, double *dbeta_in,
+                     double *de_in, double *dtau_cell) {
+  const Relax<double> rx = relax_of(rxp);
+  if (rx.eta_s > 0.0) return 0;  // g-only reverse mode does not hold with tau(n)
   Lattice L = make_lattice(dims, c_l, bc);
-  adjoint_step_g(L, tau, solid, inflow[1], inflow + 2, Sg, lam_next, lam_out, dtau, dbeta_in,
-                 de_in);
+  adjoint_step_g(L, rx, solid, inflow[1], inflow + 2, Sg, lam_next, lam_out, dtau, dbeta_in,
+                 de_in, dtau_cell);
+  return 1;
 }
 
 void ora_moments_adjoint(const int32_t *dims, double c_l, const uint8_t *solid, const double *Sg,
@@ -692,9 +775,10 @@ void ora_init_adjoint(const int32_t *dims, double c_l, const int32_t *bc, const 
 
 // Loss of a g-only forward run of nsteps from the initial fields (FP64).
 double ora_loss(const int32_t *dims, double c_l, const int32_t *bc, const double *inflow,
-                const uint8_t *solid, const double *tau, const double *e0, const double *beta0,
+                const uint8_t *solid, const OraRelax *rxp, const double *e0, const double *beta0,
                 int nsteps, const double *la, const double *lt, const double *lbe,
                 const double *lbb) {
+  const Relax<double> rx = relax_of(rxp);
   Lattice L = make_lattice(dims, c_l, bc);
   const long C = L.cells();
   double in_f[Q], in_g[Q];
@@ -703,7 +787,7 @@ double ora_loss(const int32_t *dims, double c_l, const int32_t *bc, const double
   init_state<double>(L, solid, nullptr, e0, beta0, in_f, in_g, a.data(), false);
   double *p = a.data(), *q = b.data();
   for (int t = 0; t < nsteps; ++t) {
-    step<double>(L, tau, solid, in_f, in_g, p, q, false);
+    step<double>(L, rx, solid, in_f, in_g, p, q, false);
     std::swap(p, q);
   }
   std::vector<double> e(C), bt(3 * C);
@@ -717,15 +801,23 @@ double ora_loss(const int32_t *dims, double c_l, const int32_t *bc, const double
 // d beta_in[3]}, d_e0[cells], d_beta0[3][cells]; any may be null = zero).
 // Returns dL . d (and the loss itself in *loss).
 double ora_loss_cs(const int32_t *dims, double c_l, const int32_t *bc, const double *inflow,
-                   const uint8_t *solid, const double *tau, const double *e0, const double *beta0,
-                   int nsteps, const double *la, const double *lt, const double *lbe,
-                   const double *lbb, const double *d_tau, const double *d_inflow,
-                   const double *d_e0, const double *d_beta0, double *loss) {
+                   const uint8_t *solid, const OraRelax *rxp, const double *e0,
+                   const double *beta0, int nsteps, const double *la, const double *lt,
+                   const double *lbe, const double *lbb, const double *d_tau,
+                   const double *d_inflow, const double *d_e0, const double *d_beta0,
+                   const double *d_tau_cell, double *loss) {
   const double h = 1e-30;
   Lattice L = make_lattice(dims, c_l, bc);
   const long C = L.cells();
-  std::vector<cplx> ctau(L.batch), ce0(C), cb0(3 * C);
+  const double *tau = rxp->tau;
+  std::vector<cplx> ctau(L.batch), ce0(C), cb0(3 * C), ctc;
   for (int b = 0; b < L.batch; ++b) ctau[b] = cplx(tau[b], d_tau ? h * d_tau[b] : 0.0);
+  if (rxp->tau_cell) {
+    ctc.resize(C);
+    for (long i = 0; i < C; ++i)
+      ctc[i] = cplx(rxp->tau_cell[i], d_tau_cell ? h * d_tau_cell[i] : 0.0);
+  }
+  const Relax<cplx> crx{ctau.data(), rxp->tau_cell ? ctc.data() : nullptr, 0.0, rxp->d_G};
   for (long i = 0; i < C; ++i) ce0[i] = cplx(e0[i], d_e0 ? h * d_e0[i] : 0.0);
   for (long i = 0; i < 3 * C; ++i) cb0[i] = cplx(beta0[i], d_beta0 ? h * d_beta0[i] : 0.0);
   cplx in_n(inflow[0], 0.0), in_e(inflow[1], d_inflow ? h * d_inflow[0] : 0.0);
@@ -737,7 +829,7 @@ double ora_loss_cs(const int32_t *dims, double c_l, const int32_t *bc, const dou
   init_state<cplx>(L, solid, nullptr, ce0.data(), cb0.data(), in_f, in_g, a.data(), false);
   cplx *p = a.data(), *q = b.data();
   for (int t = 0; t < nsteps; ++t) {
-    step<cplx>(L, ctau.data(), solid, in_f, in_g, p, q, false);
+    step<cplx>(L, crx, solid, in_f, in_g, p, q, false);
     std::swap(p, q);
   }
   std::vector<cplx> e(C), bt(3 * C);
@@ -752,10 +844,11 @@ double ora_loss_cs(const int32_t *dims, double c_l, const int32_t *bc, const dou
 // with respect to tau[batch], the inflow state (e_in, beta_in[3]) and the
 // initial fields e0[cells], beta0[3][cells].  Returns the loss.
 double ora_gradient(const int32_t *dims, double c_l, const int32_t *bc, const double *inflow,
-                    const uint8_t *solid, const double *tau, const double *e0,
+                    const uint8_t *solid, const OraRelax *rxp, const double *e0,
                     const double *beta0, int nsteps, const double *la, const double *lt,
                     const double *lbe, const double *lbb, double *g_tau, double *g_inflow,
-                    double *g_e0, double *g_beta0) {
+                    double *g_e0, double *g_beta0, double *g_tau_cell) {
+  const Relax<double> rx = relax_of(rxp);
   Lattice L = make_lattice(dims, c_l, bc);
   const long C = L.cells();
   const long QC = (long)Q * C;
@@ -764,7 +857,7 @@ double ora_gradient(const int32_t *dims, double c_l, const int32_t *bc, const do
   std::vector<double> states((long)(nsteps + 1) * QC);
   init_state<double>(L, solid, nullptr, e0, beta0, in_f, in_g, states.data(), false);
   for (int t = 0; t < nsteps; ++t)
-    step<double>(L, tau, solid, in_f, in_g, states.data() + t * QC, states.data() + (t + 1) * QC,
+    step<double>(L, rx, solid, in_f, in_g, states.data() + t * QC, states.data() + (t + 1) * QC,
                  false);
   const double *ST = states.data() + (long)nsteps * QC;
   std::vector<double> e(C), bt(3 * C);
@@ -784,9 +877,11 @@ double ora_gradient(const int32_t *dims, double c_l, const int32_t *bc, const do
   moments_adjoint_g(L, solid, ST, dLde.data(), dLdb.data(), lam.data());
   for (int b = 0; b < L.batch; ++b) g_tau[b] = 0.0;
   for (int k = 0; k < 4; ++k) g_inflow[k] = 0.0;
+  if (g_tau_cell)
+    for (long i = 0; i < C; ++i) g_tau_cell[i] = 0.0;
   for (int t = nsteps - 1; t >= 0; --t) {
-    adjoint_step_g(L, tau, solid, inflow[1], inflow + 2, states.data() + t * QC, lam.data(),
-                   lam2.data(), g_tau, g_inflow + 1, g_inflow);
+    adjoint_step_g(L, rx, solid, inflow[1], inflow + 2, states.data() + t * QC, lam.data(),
+                   lam2.data(), g_tau, g_inflow + 1, g_inflow, g_tau_cell);
     std::swap(lam, lam2);
   }
   init_adjoint_g(L, solid, e0, beta0, inflow[1], inflow + 2, lam.data(), g_e0, g_beta0,
@@ -794,4 +889,40 @@ double ora_gradient(const int32_t *dims, double c_l, const int32_t *bc, const do
   return Lv;
 }
 
+// Transport quantities of a stored f+g state per cell (zeros on solid
+// cells): temperature, entropy density, shear viscosity and eta/s, with each
+// cell's relaxation time from the relaxation source (for eta_s > 0 the tau
+// that the rule gives at the cell's own fields).
+void ora_transport(const int32_t *dims, double c_l, const uint8_t *solid, const double *S,
+                   const OraRelax *rxp, double *temp, double *s, double *eta, double *eta_over_s) {
+  const Relax<double> rx = relax_of(rxp);
+  int32_t bc0[6] = {0, 0, 0, 0, 0, 0};
+  Lattice L = make_lattice(dims, c_l, bc0);
+  const long C = L.cells();
+  const long per = (long)L.n[0] * L.n[1] * L.n[2];
+  for (long i = 0; i < C; ++i) {
+    temp[i] = s[i] = eta[i] = eta_over_s[i] = 0.0;
+    if (solid && solid[i]) continue;
+    double pf[Q], pg[Q];
+    for (int q = 0; q < Q; ++q) {
+      pf[q] = S[(long)q * C + i];
+      pg[q] = S[(long)(Q + q) * C + i];
+    }
+    double N, E, M[3], n, eps, beta[3];
+    moment_sums(pf, pg, c_l, &N, &E, M);
+    invert(N, E, M, &n, &eps, beta);
+    double tau = rx.tau_cell ? rx.tau_cell[i] : rx.tau[i / per];
+    if (rx.eta_s > 0.0) tau = tau_for_eta_s(pf, pg, c_l, rx.eta_s, rx.d_G);
+    transport(n, eps, beta, tau, c_l, rx.d_G, &temp[i], &s[i], &eta[i]);
+    eta_over_s[i] = eta[i] / s[i];
+  }
+}
+
 }  // extern "C"
+
+namespace {
+Relax<double> relax_of(const void *r) {
+  const OraRelax *x = static_cast<const OraRelax *>(r);
+  return Relax<double>{x->tau, x->tau_cell, x->eta_s, x->d_G};
+}
+}  // namespace

@@ -14,7 +14,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "rlb_oracle.cpp")
 PINS = [os.path.join(ROOT, "tests", f) for f in
-        ("test_oracle_pins.py", "test_oracle_riemann.py", "test_oracle_gradients.py")]
+        ("test_oracle_pins.py", "test_oracle_riemann.py", "test_oracle_gradients.py",
+         "test_oracle_transport.py")]
 
 MUTATIONS = {
     "drop_quadratic_term": ("6.0 * cu * cu / (cl2 * cl2)", "0.0 * cu * cu / (cl2 * cl2)"),
@@ -36,6 +37,15 @@ MUTATIONS = {
                             "for (int q = 0; q < Q; ++q) mu += lam[q] * J[p][q];"),
     "inflow_not_held": ("      if (bc[a][0] == BC_INFLOW && c[a] == 0) return true;",
                         "      if (bc[a][0] == BC_INFLOW && c[a] == 0 && false) return true;"),
+    "eta_without_half_step": ("(tau * dt - dt / 2.0)", "(tau * dt)"),
+    "entropy_log_sign": ("*s = 4.0 * n - n * log(lam);", "*s = 4.0 * n + n * log(lam);"),
+    "n_eq_power": ("T n_eq = d_G * Tm * Tm * Tm / (pi * pi);", "T n_eq = d_G * Tm * Tm / (pi * pi);"),
+    "temperature_coefficient": ("T Tm = eps / (3.0 * n);", "T Tm = eps / (4.0 * n);"),
+    "tau_cell_by_instance": ("T tau = rx.tau_cell ? rx.tau_cell[i] : rx.tau[b];",
+                             "T tau = rx.tau_cell ? rx.tau_cell[b] : rx.tau[b];"),
+    "eta_s_rule_uses_n": ("T eta = eta_s * s;", "T eta = eta_s * n;"),
+    "tau_cell_gradient_overwritten": ("if (dtau_cell) dtau_cell[i] += s;",
+                                      "if (dtau_cell) dtau_cell[i] = s;"),
 }
 
 
