@@ -287,6 +287,27 @@ def main():
                                             "speedup_vs_f64": round(t64 / dtb, 3)}
             del b
         out["mixed_precision_256cube"] = extras
+        # relaxation variants on the FP64 256^3 box: a per-cell tau field (reads
+        # 8 more bytes per cell) and tau set per update to hold eta/s (adds the
+        # transport arithmetic: a log, a sqrt and divisions per cell)
+        relax = {}
+        for name in ("tau_field", "eta_s_held"):
+            b = ri.periodic_box(storage=ri.F64)
+            per_cell = 2 * Q * 2 * 8
+            if name == "tau_field":
+                b.tau_cell = np.random.default_rng(3).uniform(0.55, 0.8, b.cells)
+                per_cell += 8
+            else:
+                b.eta_s = 0.1
+            dtb, cnt = bench_forward(b, box_steps, 5)
+            gbs = b.cells * per_cell / (dtb / box_steps) / 1e9
+            relax[name] = {"ms_per_step": round(1e3 * dtb / box_steps, 4),
+                           "mlups": round(b.cells * box_steps / dtb / 1e6, 1),
+                           "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                           "vs_per_instance_tau": round(t64 / dtb, 3),
+                           "unphysical_updates": int(cnt[0])}
+            del b
+        out["relaxation_variants_256cube_f64"] = relax
         # gradient of a 60-step sphere run (the flow stays physical that long):
         # reverse sweep per step (recompute + adjoint) against one forward step
         for st in (ri.F64, ri.F32):

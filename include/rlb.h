@@ -220,6 +220,50 @@ rlb_status rlb_init_adjoint(rlb_solver *h, const double *e0, const double *beta0
                             const void *lam_0, double *dL_de0, double *dL_dbeta0,
                             double *dL_dbeta_in, double *dL_de_in);
 
+/* Per-cell relaxation times tau(x) (device double [cells], copied), in
+ * units of dt, replacing the per-instance tau of rlb_init in every later
+ * forward and reverse step; NULL restores the per-instance tau.  The
+ * viscosity relation at the end of the equilibrium section,
+ * eta = (4/9) gamma^2 e (tau - dt/2) c_l^2, then holds cell by cell.
+ * Synchronises (the field is validated): RLB_EINVAL if a non-solid cell's
+ * tau is not > 1/2 or NaN, and the previous field (or none) stays in force.
+ * While a field is set the reverse steps also accumulate dL/dtau(x) per cell
+ * (see rlb_adjoint_flush_tau_field); setting a field clears that
+ * accumulator.  Library-owned memory: 16 bytes per cell. */
+rlb_status rlb_set_tau_field(rlb_solver *h, const double *tau_cell);
+
+/* Hold eta/s fixed (the shock-tube section characterises its runs by eta/s):
+ * with eta_over_s > 0 every later f+g step sets each update's tau from its
+ * pre-collision moments of both populations,
+ *   tau = 1/2 + 9 (eta/s) s / (4 gamma^2 e c_l),
+ *   s = 4n - n ln(n / n_eq), n_eq = d_G T^3 / pi^2, T = e / (3n),
+ * overriding the per-instance tau and any tau field.  An update whose rule
+ * gives tau <= 1/2 (or NaN) counts as unphysical (rlb_counters).  tau then
+ * depends on n, i.e. on f, so rlb_step_g, rlb_advance_g, rlb_trajectory_g,
+ * rlb_adjoint_step and rlb_adjoint_sweep return RLB_EINVAL while it is on.
+ * eta_over_s = 0 turns it off.  RLB_EINVAL for eta_over_s < 0, d_G <= 0 or
+ * non-finite values.  Host-only (no device work). */
+rlb_status rlb_hold_eta_over_s(rlb_solver *h, double eta_over_s, double d_G);
+
+/* Transport quantities of the current state per cell (device double
+ * [cells], any may be NULL; zeros on solid cells), from the cell's fields
+ * (n, e, beta) and its tau (per instance, tau field, or with eta/s held the
+ * rule's tau at these fields): T = e/(3n); s = 4n - n ln(n/n_eq) with
+ * n_eq = d_G T^3/pi^2; eta = (4/9) gamma^2 e c_l (tau - 1/2); eta_over_s.
+ * d_G > 0 (16 for gluons); while eta/s is held it must equal the d_G given
+ * there.  Asynchronous. */
+rlb_status rlb_transport(rlb_solver *h, double d_G, double *T, double *s, double *eta,
+                         double *eta_over_s);
+
+/* Add the per-cell tau gradient accumulated by the reverse steps since the
+ * field was set or last handed over, dL/dtau(x), to dL_dtau_cell (device
+ * double [cells]) and clear the accumulator.  Contributions are added per
+ * cell in step order, so the result is bitwise reproducible.  RLB_EINVAL
+ * when no tau field is set.  (The per-instance dL_dtau of the reverse steps
+ * is then the derivative for a uniform shift of the instance's field: the
+ * sum of dL/dtau(x) over its cells.) */
+rlb_status rlb_adjoint_flush_tau_field(rlb_solver *h, double *dL_dtau_cell);
+
 /* Release the solver's own memory (not pop_a / pop_b).  Synchronises. */
 rlb_status rlb_destroy(rlb_solver *h);
 

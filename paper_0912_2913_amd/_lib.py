@@ -22,7 +22,8 @@ EXPORTS = (
     "rlb_buffer_layout", "rlb_init", "rlb_step", "rlb_step_g", "rlb_current", "rlb_moments",
     "rlb_fields_g", "rlb_counters", "rlb_adjoint_step", "rlb_moments_adjoint", "rlb_init_adjoint",
     "rlb_destroy", "rlb_status_string", "rlb_last_error", "rlb_advance_g", "rlb_trajectory_g",
-    "rlb_adjoint_sweep", "rlb_adjoint_flush",
+    "rlb_adjoint_sweep", "rlb_adjoint_flush", "rlb_set_tau_field", "rlb_hold_eta_over_s",
+    "rlb_transport", "rlb_adjoint_flush_tau_field",
 )
 
 
@@ -79,6 +80,10 @@ def lib():
     L.rlb_adjoint_sweep.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp,
                                     ctypes.POINTER(vp)]
     L.rlb_adjoint_flush.argtypes = [vp, vp, vp, vp]
+    L.rlb_set_tau_field.argtypes = [vp, vp]
+    L.rlb_hold_eta_over_s.argtypes = [vp, ctypes.c_double, ctypes.c_double]
+    L.rlb_transport.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
+    L.rlb_adjoint_flush_tau_field.argtypes = [vp, vp]
     L.rlb_moments_adjoint.argtypes = [vp, vp, vp, vp, vp]
     L.rlb_init_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.rlb_destroy.argtypes = [vp]
@@ -89,7 +94,8 @@ def lib():
     for name in ("rlb_buffer_layout", "rlb_init", "rlb_step", "rlb_step_g", "rlb_current",
                  "rlb_moments", "rlb_fields_g", "rlb_counters", "rlb_adjoint_step", "rlb_moments_adjoint",
                  "rlb_init_adjoint", "rlb_destroy", "rlb_advance_g", "rlb_trajectory_g",
-                 "rlb_adjoint_sweep", "rlb_adjoint_flush"):
+                 "rlb_adjoint_sweep", "rlb_adjoint_flush", "rlb_set_tau_field",
+                 "rlb_hold_eta_over_s", "rlb_transport", "rlb_adjoint_flush_tau_field"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -93,39 +93,53 @@ class GRun:
             if res is lb:
                 la, lb = lb, la
         sv.adjoint_flush(dtau, dbin, dein)
+        dtc = None
+        if sv.tau_cell is not None:
+            dtc = torch.zeros(sv.cells, dtype=torch.float64, device=dev)
+            sv.adjoint_flush_tau_field(dtc)
         de0 = torch.empty(sv.cells, dtype=torch.float64, device=dev)
         db0 = torch.empty((3, sv.cells), dtype=torch.float64, device=dev)
         sv.init_adjoint(la, de0, db0, dbin, dein)
-        return dtau, dein, dbin, de0, db0
+        return dtau, dein, dbin, de0, db0, dtc
 
 
 class RLBFunction(torch.autograd.Function):
-    """(tau[batch], e_in[1], beta_in[3], e0[cells], beta0[3, cells]) -> (e_T, beta_T).
+    """(tau[batch], e_in[1], beta_in[3], e0[cells], beta0[3, cells], tau_cell[cells] or None)
+    -> (e_T, beta_T).
 
     ``setup`` fixes everything else (extents, boundaries, storage, n0, solid);
     ``steps`` is T and ``checkpoint`` is "sqrt", "store_all" or a segment length.
-    Inputs may live on any device; the run uses ``setup``'s GPU (cuda:0).
+    With ``tau_cell`` the per-cell relaxation times replace tau (whose gradient
+    is then the one for a uniform shift of each instance's field).  Inputs may
+    live on any device; the run uses ``setup``'s GPU (cuda:0).
     """
 
     @staticmethod
-    def forward(ctx, tau, e_in, beta_in, e0, beta0, setup, steps, checkpoint="sqrt"):
+    def forward(ctx, tau, e_in, beta_in, e0, beta0, tau_cell, setup, steps, checkpoint="sqrt"):
+        if getattr(setup, "eta_s", 0.0) > 0.0:
+            raise ValueError("the reverse sweep needs a state-independent tau (eta/s not held)")
         tau_h = tau.detach().double().cpu().numpy()
         inflow = list(setup.inflow)
         inflow[1] = float(e_in.detach().double().reshape(-1)[0])
         inflow[2:5] = [float(v) for v in beta_in.detach().double().reshape(-1).cpu()]
         s = replace(setup, tau=tau_h, inflow=tuple(inflow),
                     e0=e0.detach().double().cpu().numpy().reshape(-1),
-                    beta0=beta0.detach().double().cpu().numpy().reshape(3, -1))
+                    beta0=beta0.detach().double().cpu().numpy().reshape(3, -1), tau_cell=None)
         sv = Solver(s)
+        if tau_cell is not None:
+            sv.set_tau_field(tau_cell.detach())
         run = GRun(sv, int(steps), segment_length(int(steps), checkpoint))
-        need = any(ctx.needs_input_grad[:5])
+        need = any(ctx.needs_input_grad[:6])
         e, b = run.forward(keep=need)
         if not need:
             sv.close()
             run = None
         ctx.run = run
-        ctx.devs = (tau.device, e_in.device, beta_in.device, e0.device, beta0.device)
-        ctx.shapes = (tau.shape, e_in.shape, beta_in.shape, e0.shape, beta0.shape)
+        ctx.has_tc = tau_cell is not None
+        ctx.devs = (tau.device, e_in.device, beta_in.device, e0.device, beta0.device,
+                    tau_cell.device if tau_cell is not None else None)
+        ctx.shapes = (tau.shape, e_in.shape, beta_in.shape, e0.shape, beta0.shape,
+                      tau_cell.shape if tau_cell is not None else None)
         return e.to(e0.device), b.to(beta0.device)
 
     @staticmethod
@@ -136,27 +150,30 @@ class RLBFunction(torch.autograd.Function):
             g_e = torch.zeros(run.sv.cells, dtype=torch.float64, device=dev)
         if g_b is None:
             g_b = torch.zeros((3, run.sv.cells), dtype=torch.float64, device=dev)
-        dtau, dein, dbin, de0, db0 = run.backward(g_e.to(dev, torch.float64),
-                                                  g_b.to(dev, torch.float64))
+        dtau, dein, dbin, de0, db0, dtc = run.backward(g_e.to(dev, torch.float64),
+                                                       g_b.to(dev, torch.float64))
         outs = []
-        for g, d, sh in zip((dtau, dein, dbin, de0, db0), ctx.devs, ctx.shapes):
-            outs.append(g.to(d).reshape(sh))
+        for g, d, sh in zip((dtau, dein, dbin, de0, db0, dtc), ctx.devs, ctx.shapes):
+            outs.append(None if g is None else g.to(d).reshape(sh))
         run.sv.close()
         ctx.run = None
         return (*outs, None, None, None)
 
 
 def rlb_run(setup, steps: int, tau=None, e_in=None, beta_in=None, e0=None, beta0=None,
-            checkpoint="sqrt", device="cuda:0"):
+            checkpoint="sqrt", device="cuda:0", tau_cell=None):
     """Differentiable run: returns (e_T, beta_T) device float64 tensors.  Any
-    parameter left None is taken from ``setup`` as a constant."""
+    parameter left None is taken from ``setup`` as a constant (tau_cell:
+    ``setup.tau_cell`` if set, else the per-instance tau)."""
     f64 = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64), device=device)
     tau = f64(np.asarray(setup.tau).reshape(-1)) if tau is None else tau
     e_in = f64([setup.inflow[1]]) if e_in is None else e_in
     beta_in = f64(setup.inflow[2:5]) if beta_in is None else beta_in
     e0 = f64(np.asarray(setup.e0).reshape(-1)) if e0 is None else e0
     beta0 = f64(np.asarray(setup.beta0).reshape(3, -1)) if beta0 is None else beta0
-    return RLBFunction.apply(tau, e_in, beta_in, e0, beta0, setup, steps, checkpoint)
+    if tau_cell is None and getattr(setup, "tau_cell", None) is not None:
+        tau_cell = f64(np.asarray(setup.tau_cell).reshape(-1))
+    return RLBFunction.apply(tau, e_in, beta_in, e0, beta0, tau_cell, setup, steps, checkpoint)
 
 
 def surface_mask(setup) -> np.ndarray:

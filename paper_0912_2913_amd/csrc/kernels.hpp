@@ -90,7 +90,41 @@ struct Phys {
   double n_ref, e_ref;          // zero unless the storage holds deviations
   const double *omega;          // [batch] 1/tau
   const uint8_t *cls;           // [cells] class bits, or null (no obstacle)
+  const double *omega_cell;     // [cells] 1/tau(x) of a per-cell tau field, or null
+  double *dtau_cell;            // [cells] reverse-sweep dL/dtau(x) accumulator, or null
+  double eta_s, d_G;            // eta_s > 0: tau from the local state holds eta/s
 };
+
+// Relaxation rate of cell c from the per-cell field or its instance.
+__device__ __forceinline__ double omega_of(const Phys &ph, int b, long long idx) {
+  return ph.omega_cell ? ph.omega_cell[idx] : ph.omega[b];
+}
+
+// Transport quantities of the shock-tube section from the fields of a cell:
+// T = e / (3n), n_eq = d_G T^3 / pi^2, lambda = n / n_eq,
+// s = 4n - n ln(lambda); and the viscosity relation of the equilibrium
+// section, eta = (4/9) gamma^2 e (tau - dt/2) c_l^2 with tau in units of
+// dt = dx / c_l, i.e. eta = (4/9) gamma^2 e c_l (tau - 1/2).
+struct Transport {
+  double T, s, gamma2;
+};
+
+__device__ __forceinline__ Transport transport_of(double n, double e, double b2, double d_G) {
+  Transport t;
+  t.T = e / (3.0 * n);
+  const double n_eq = d_G * t.T * t.T * t.T * (1.0 / (M_PI * M_PI));
+  t.s = n * (4.0 - log(n / n_eq));
+  t.gamma2 = 1.0 / (1.0 - b2);
+  return t;
+}
+
+// 1/tau holding eta/s = eta_s at (n, e, beta): the viscosity relation solved
+// for tau with eta = eta_s * s.
+__device__ __forceinline__ double omega_for_eta_s(const Phys &ph, double n, double e, double b2) {
+  const Transport t = transport_of(n, e, b2, ph.d_G);
+  const double tau = 0.5 + (9.0 / 4.0) * ph.eta_s * t.s / (t.gamma2 * e * ph.c);
+  return 1.0 / tau;
+}
 
 // Inflow state for the adjoint of the held face (e_in, beta_in).
 struct InflowState {
@@ -421,8 +455,9 @@ __device__ __forceinline__ void stream_store(El *p, El v) {
 // (src/dst then address g blocks).  HELD = false is the instantiation for
 // lattices with neither solid cells nor an inflow plane: the held-value
 // selection and the bounce-back test compile away (the 16-bit forms are
-// issue-bound, so those instructions cost time there).
-template <int ST, class TC, bool DO_F, bool HELD>
+// issue-bound, so those instructions cost time there).  ETA_S (f+g steps
+// only) sets each update's tau from its pre-collision moments to hold eta/s.
+template <int ST, class TC, bool DO_F, bool HELD, bool ETA_S = false>
 __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
                                                 const typename Codec<ST, TC>::elem *__restrict__ src,
                                                 typename Codec<ST, TC>::elem *__restrict__ dst,
@@ -458,19 +493,30 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
   const Inv iv = invert(ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
                         ph.c * (double)sz);
   EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
-  const T om = (T)ph.omega[c.b];
+  double omd = omega_of(ph, c.b, c.idx);
+  bool bad = iv.bad;
+  double N = 0.0;
+  if (DO_F) {
+    T sN = (T)0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) sN += pf[q];
+    N = ph.n_ref + (double)sN;
+    if (ETA_S) {
+      // tau from the pre-collision moments of this update (n = N / gamma)
+      const double b2 = iv.bx * iv.bx + iv.by * iv.by + iv.bz * iv.bz;
+      omd = omega_for_eta_s(ph, N * sqrt(1.0 - b2), iv.eps, b2);
+      bad = bad || !(omd > 0.0 && omd < 2.0);  // needs tau > 1/2
+    }
+  }
+  const T om = (T)omd;
   const El zero = Cd::enc((T)0);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const El v = Cd::enc(pg[q] + om * (geq_dev(k, q) - pg[q]));
     stream_store(&gd[at(q, c.idx)], held ? (solid ? zero : in_eq.v[Q + q]) : v);
   }
-  count_lanes(iv.bad && !held, counters, 0);
+  count_lanes(bad && !held, counters, 0);
   if (DO_F) {
-    T sN = (T)0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) sN += pf[q];
-    const double N = ph.n_ref + (double)sN;
     k.N = (T)N;
     k.Nd = (T)(N - ph.n_ref);
 #pragma unroll
@@ -599,6 +645,73 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const Geom g, const Phys ph,
     if (threadIdx.x == 0)
       for (int k = 0; k < 5; ++k) part[(size_t)c.L * 5 + k] = out[k];
   }
+}
+
+// Transport quantities of a stored f+g state per cell (zeros on solid
+// cells): temperature, entropy density, shear viscosity and eta/s, each cell
+// with its relaxation time (per-cell field, instance, or the eta/s rule at
+// the cell's fields).  Any output may be null.
+template <int ST, class TC>
+__global__ __launch_bounds__(BLOCK) void k_transport(const Geom g, const Phys ph,
+                                                     const typename Codec<ST, TC>::elem *__restrict__ Sf,
+                                                     const typename Codec<ST, TC>::elem *__restrict__ Sg,
+                                                     double *__restrict__ temp, double *__restrict__ ent,
+                                                     double *__restrict__ eta, double *__restrict__ eos) {
+  using Cd = Codec<ST, TC>;
+  const Cell c = decode_cell(g);
+  if (!c.active) return;
+  double vT = 0.0, vs = 0.0, veta = 0.0, veos = 0.0;
+  if (!solid_at(ph, c.idx)) {
+    double N = ph.n_ref, Eg = ph.e_ref, sx, sy, sz, gv[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      N += (double)Cd::dec(Sf[at(q, c.idx)]);
+      gv[q] = (double)Cd::dec(Sg[at(q, c.idx)]);
+      Eg += gv[q];
+    }
+    mirror_sums(gv, sx, sy, sz);
+    const Inv iv = invert(Eg, ph.c * sx, ph.c * sy, ph.c * sz);
+    const double b2 = iv.bx * iv.bx + iv.by * iv.by + iv.bz * iv.bz;
+    const double n = N * sqrt(1.0 - b2);
+    const double om = ph.eta_s > 0.0 ? omega_for_eta_s(ph, n, iv.eps, b2) : omega_of(ph, c.b, c.idx);
+    const Transport t = transport_of(n, iv.eps, b2, ph.d_G);
+    vT = t.T;
+    vs = t.s;
+    veta = (4.0 / 9.0) * t.gamma2 * iv.eps * ph.c * (1.0 / om - 0.5);
+    veos = veta / vs;
+  }
+  if (temp) temp[c.idx] = vT;
+  if (ent) ent[c.idx] = vs;
+  if (eta) eta[c.idx] = veta;
+  if (eos) eos[c.idx] = veos;
+}
+
+// omega(x) = 1/tau(x) of a per-cell tau field; counts (into *bad) the
+// non-solid cells whose tau is not > 1/2 (or NaN).
+__global__ __launch_bounds__(BLOCK) void k_set_omega_cell(const Geom g, const Phys ph,
+                                                          const double *__restrict__ tau,
+                                                          double *__restrict__ omega,
+                                                          unsigned long long *__restrict__ bad) {
+  const Cell c = decode_cell(g);
+  bool flag = false;
+  if (c.active) {
+    const double t = tau[c.idx];
+    const bool solid = solid_at(ph, c.idx);
+    flag = !solid && !(t > 0.5);
+    omega[c.idx] = solid ? 0.0 : 1.0 / t;
+  }
+  const unsigned long long m = __ballot(flag);
+  if (m != 0ull && (threadIdx.x & 63u) == (unsigned)(__ffsll((long long)m) - 1))
+    atomicAdd(bad, (unsigned long long)__popcll(m));
+}
+
+// out[i] += acc[i]; acc[i] = 0 over the cells (hand the per-cell gradient over).
+__global__ __launch_bounds__(BLOCK) void k_take_cell_grad(long long cells, double *__restrict__ acc,
+                                                          double *__restrict__ out) {
+  const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= cells) return;
+  out[i] += acc[i];
+  acc[i] = 0.0;
 }
 
 // Per-instance, fixed-order reduction of per-workgroup [5] partials: one
@@ -857,10 +970,11 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
     for (int q = 0; q < Q; ++q) pre[q] = (double)Cd::dec(S[at(q, src_fast(g, c, fc, q))]);
 #pragma unroll
     for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, c.idx)];
-    const LocalAdjoint a = adjoint_local(ph, ph.omega[c.b], pre, lam);
+    const LocalAdjoint a = adjoint_local(ph, omega_of(ph, c.b, c.idx), pre, lam);
 #pragma unroll
     for (int q = 0; q < Q; ++q) lam_out[at(q, src_fast(g, c, fc, q))] = adjoint_mu(a, lam[q], q);
     acc[0] = a.dtau;
+    if (ph.dtau_cell) ph.dtau_cell[c.idx] += a.dtau;
   }
   double out[5];
   block_sum<5>(acc, out);
@@ -912,7 +1026,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_general(
       }
 #pragma unroll
       for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, c.idx)];
-      const LocalAdjoint a = adjoint_local(ph, ph.omega[c.b], pre, lam);
+      const LocalAdjoint a = adjoint_local(ph, omega_of(ph, c.b, c.idx), pre, lam);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const double mu = adjoint_mu(a, lam[q], q);
@@ -925,6 +1039,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_general(
           lam_out[at(q, p.idx)] = mu;
       }
       acc[0] = a.dtau;
+      if (ph.dtau_cell) ph.dtau_cell[c.idx] += a.dtau;
     }
   }
   double out[5];

@@ -42,6 +42,9 @@ struct rlb_solver {
   bool glist_ready;
   bool rev_pending;  // reverse-step partials accumulated and not yet reduced
   bool held;         // solid cells or an inflow plane exist (held cells)
+  double *d_omega_cell;       // per-cell 1/tau of a tau field (or null)
+  double *d_dtau_cell;        // per-cell dL/dtau(x) accumulated by the reverse steps
+  unsigned long long *d_bad;  // validation counter of rlb_set_tau_field
 };
 
 namespace {
@@ -222,14 +225,21 @@ rlb_status launch_steps(rlb_solver *h, int nsteps) {
   using El = typename Codec<ST, TC>::elem;
   const HeldEq<El> in_eq = held_eq<El>(h);
   for (int s = 0; s < nsteps; ++s) {
-    if (h->held)
+    const El *src = (const El *)h->pop[h->cur];
+    El *dst = (El *)h->pop[1 - h->cur];
+    const bool etas = h->ph.eta_s > 0.0;
+    if (h->held && etas)
+      hipLaunchKernelGGL((k_step<ST, TC, true, true, true>), dim3(grid_blocks(h)), dim3(BLOCK), 0,
+                         h->stream, h->g, h->ph, src, dst, in_eq, h->d_counters);
+    else if (h->held)
       hipLaunchKernelGGL((k_step<ST, TC, true, true>), dim3(grid_blocks(h)), dim3(BLOCK), 0,
-                         h->stream, h->g, h->ph, (const El *)h->pop[h->cur],
-                         (El *)h->pop[1 - h->cur], in_eq, h->d_counters);
+                         h->stream, h->g, h->ph, src, dst, in_eq, h->d_counters);
+    else if (etas)
+      hipLaunchKernelGGL((k_step<ST, TC, true, false, true>), dim3(grid_blocks(h)), dim3(BLOCK),
+                         0, h->stream, h->g, h->ph, src, dst, in_eq, h->d_counters);
     else
       hipLaunchKernelGGL((k_step<ST, TC, true, false>), dim3(grid_blocks(h)), dim3(BLOCK), 0,
-                         h->stream, h->g, h->ph, (const El *)h->pop[h->cur],
-                         (El *)h->pop[1 - h->cur], in_eq, h->d_counters);
+                         h->stream, h->g, h->ph, src, dst, in_eq, h->d_counters);
     h->cur = 1 - h->cur;
   }
   RLB_HIP(hipGetLastError());
@@ -247,6 +257,16 @@ rlb_status launch_step_g(rlb_solver *h, const void *src, void *dst) {
     hipLaunchKernelGGL((k_step<ST, TC, false, false>), dim3(grid_blocks(h)), dim3(BLOCK), 0,
                        h->stream, h->g, h->ph, (const El *)src, (El *)dst, held_eq<El>(h),
                        h->d_counters);
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
+}
+
+template <int ST, class TC>
+rlb_status launch_transport(rlb_solver *h, double *T, double *ent, double *eta, double *eos) {
+  using El = typename Codec<ST, TC>::elem;
+  const El *S = (const El *)h->pop[h->cur];
+  hipLaunchKernelGGL((k_transport<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+                     h->ph, S, S + (size_t)Q * h->g.qs, T, ent, eta, eos);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -421,6 +441,9 @@ void free_solver(rlb_solver *h) {
   if (h->d_glist) (void)hipFree(h->d_glist);
   if (h->d_gstart) (void)hipFree(h->d_gstart);
   if (h->d_part2) (void)hipFree(h->d_part2);
+  if (h->d_omega_cell) (void)hipFree(h->d_omega_cell);
+  if (h->d_dtau_cell) (void)hipFree(h->d_dtau_cell);
+  if (h->d_bad) (void)hipFree(h->d_bad);
   delete h;
 }
 
@@ -480,6 +503,7 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
   const bool dev = p->storage >= ST_F32DEV;
   ph.n_ref = dev ? p->n_ref : 0.0;
   ph.e_ref = dev ? p->e_ref : 0.0;
+  ph.d_G = 16.0;
   h->in.e = p->inflow_e;
   h->in.bx = p->inflow_beta[0];
   h->in.by = p->inflow_beta[1];
@@ -543,6 +567,8 @@ rlb_status rlb_step(rlb_solver *h, int32_t nsteps) {
 
 rlb_status rlb_step_g(rlb_solver *h, const void *g_src, void *g_dst) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->ph.eta_s > 0.0)
+    return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   if (!g_src || !g_dst || g_src == g_dst) return fail(RLB_EINVAL, "g_src/g_dst invalid");
   RLB_DISPATCH(h, launch_step_g, h, g_src, g_dst);
 }
@@ -604,6 +630,8 @@ rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *la
                             void *lam_out, double *dL_dtau, double *dL_dbeta_in,
                             double *dL_de_in) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->ph.eta_s > 0.0)
+    return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   if (!g_state_t || !lam_next || !lam_out || lam_next == lam_out)
     return fail(RLB_EINVAL, "adjoint buffers invalid");
   rlb_status s = prepare_adjoint(h);
@@ -620,6 +648,8 @@ rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *la
 rlb_status rlb_adjoint_sweep(rlb_solver *h, const void *g_seq, int64_t seq_stride, int32_t n,
                              void *lam_a, void *lam_b, void **lam_result) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->ph.eta_s > 0.0)
+    return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   if (n < 0 || !lam_a || !lam_b || lam_a == lam_b || !lam_result || (n > 0 && !g_seq) ||
       seq_stride < 0)
     return fail(RLB_EINVAL, "adjoint sweep arguments invalid");
@@ -649,6 +679,8 @@ rlb_status rlb_adjoint_flush(rlb_solver *h, double *dL_dtau, double *dL_dbeta_in
 
 rlb_status rlb_advance_g(rlb_solver *h, const void *g_src, void *g_dst, void *g_tmp, int32_t n) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->ph.eta_s > 0.0)
+    return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   if (n < 0 || !g_src || !g_dst || g_src == g_dst || (n > 1 && (!g_tmp || g_tmp == g_src ||
                                                                  g_tmp == g_dst)))
     return fail(RLB_EINVAL, "advance arguments invalid");
@@ -670,6 +702,8 @@ rlb_status rlb_advance_g(rlb_solver *h, const void *g_src, void *g_dst, void *g_
 
 rlb_status rlb_trajectory_g(rlb_solver *h, void *g_seq, int64_t seq_stride, int32_t n) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->ph.eta_s > 0.0)
+    return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   const int64_t need = (int64_t)Q * h->g.qs * (int64_t)h->elem;
   if (n < 1 || !g_seq || seq_stride < need) return fail(RLB_EINVAL, "trajectory arguments invalid");
   for (int j = 1; j < n; ++j) {
@@ -698,6 +732,85 @@ rlb_status rlb_init_adjoint(rlb_solver *h, const double *e0, const double *beta0
     return fail(RLB_EINVAL, "a required pointer is NULL");
   RLB_DISPATCH(h, launch_init_adjoint, h, e0, beta0, lam_0, dL_de0, dL_dbeta0, dL_dbeta_in,
                dL_de_in);
+}
+
+rlb_status rlb_set_tau_field(rlb_solver *h, const double *tau_cell) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  const long long cells = (long long)h->g.batch * h->g.per;
+  if (!tau_cell) {
+    RLB_HIP(hipStreamSynchronize(h->stream));
+    if (h->d_omega_cell) (void)hipFree(h->d_omega_cell);
+    if (h->d_dtau_cell) (void)hipFree(h->d_dtau_cell);
+    h->d_omega_cell = h->d_dtau_cell = nullptr;
+    h->ph.omega_cell = nullptr;
+    h->ph.dtau_cell = nullptr;
+    return RLB_OK;
+  }
+  if (!h->d_bad) RLB_HIP(hipMalloc(&h->d_bad, sizeof(unsigned long long)));
+  double *om = nullptr;
+  RLB_HIP(hipMalloc(&om, sizeof(double) * (size_t)cells));
+  unsigned long long nbad = 0;
+  hipError_t e = hipMemsetAsync(h->d_bad, 0, sizeof(unsigned long long), h->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_set_omega_cell, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+                       h->ph, tau_cell, om, h->d_bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&nbad, h->d_bad, sizeof(nbad), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(om);
+    return fail(RLB_EDEVICE, std::string("rlb_set_tau_field: ") + hipGetErrorString(e));
+  }
+  if (nbad > 0) {
+    (void)hipFree(om);
+    return fail(RLB_EINVAL, "tau field: " + std::to_string(nbad) +
+                                " non-solid cells with tau not > 1/2 (field unchanged)");
+  }
+  if (h->d_omega_cell) (void)hipFree(h->d_omega_cell);
+  h->d_omega_cell = om;
+  h->ph.omega_cell = om;
+  if (!h->d_dtau_cell) RLB_HIP(hipMalloc(&h->d_dtau_cell, sizeof(double) * (size_t)cells));
+  RLB_HIP(hipMemsetAsync(h->d_dtau_cell, 0, sizeof(double) * (size_t)cells, h->stream));
+  h->ph.dtau_cell = h->d_dtau_cell;
+  return RLB_OK;
+}
+
+rlb_status rlb_hold_eta_over_s(rlb_solver *h, double eta_over_s, double d_G) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (!(eta_over_s >= 0.0) || !std::isfinite(eta_over_s) || !(d_G > 0.0) || !std::isfinite(d_G))
+    return fail(RLB_EINVAL, "eta_over_s must be >= 0 and d_G > 0 (both finite)");
+  h->ph.eta_s = eta_over_s;
+  h->ph.d_G = d_G;
+  return RLB_OK;
+}
+
+rlb_status rlb_transport(rlb_solver *h, double d_G, double *T, double *s, double *eta,
+                         double *eta_over_s) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (!(d_G > 0.0) || !std::isfinite(d_G)) return fail(RLB_EINVAL, "d_G must be > 0");
+  if (h->ph.eta_s > 0.0 && d_G != h->ph.d_G)
+    return fail(RLB_EINVAL, "d_G differs from the one eta/s is held with");
+  const double keep = h->ph.d_G;
+  h->ph.d_G = d_G;
+  auto launch = [&]() -> rlb_status {
+    RLB_DISPATCH(h, launch_transport, h, T, s, eta, eta_over_s);
+  };
+  rlb_status st = launch();
+  h->ph.d_G = keep;
+  return st;
+}
+
+rlb_status rlb_adjoint_flush_tau_field(rlb_solver *h, double *dL_dtau_cell) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (!h->d_dtau_cell) return fail(RLB_EINVAL, "no tau field is set");
+  if (!dL_dtau_cell) return fail(RLB_EINVAL, "dL_dtau_cell is NULL");
+  const long long cells = (long long)h->g.batch * h->g.per;
+  hipLaunchKernelGGL(k_take_cell_grad, dim3((unsigned)((cells + BLOCK - 1) / BLOCK)), dim3(BLOCK),
+                     0, h->stream, cells, h->d_dtau_cell, dL_dtau_cell);
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
 }
 
 rlb_status rlb_destroy(rlb_solver *h) {

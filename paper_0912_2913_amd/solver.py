@@ -112,6 +112,11 @@ class Solver:
                                   _ptr(self.pop[0]), _ptr(self.pop[1]),
                                   ctypes.c_void_p(self.stream.cuda_stream)), "rlb_init")
         self.h = h
+        self.tau_cell = None
+        if getattr(s, "tau_cell", None) is not None:
+            self.set_tau_field(s.tau_cell)
+        if getattr(s, "eta_s", 0.0) > 0.0:
+            self.hold_eta_over_s(s.eta_s, getattr(s, "d_G", 16.0))
 
     # ------------------------------------------------------------------ forward
     def step(self, nsteps: int = 1):
@@ -160,6 +165,37 @@ class Solver:
     def adjoint_flush(self, dtau=None, dbeta_in=None, de_in=None):
         check(_lib.lib().rlb_adjoint_flush(self.h, _ptr(dtau), _ptr(dbeta_in), _ptr(de_in)),
               "rlb_adjoint_flush")
+
+    # ------------------------------------------------------------- relaxation
+    def set_tau_field(self, tau_cell):
+        """Per-cell relaxation times (array/tensor [cells]) or None for the
+        per-instance tau."""
+        if tau_cell is None:
+            check(_lib.lib().rlb_set_tau_field(self.h, None), "rlb_set_tau_field")
+            self.tau_cell = None
+            return
+        t = torch.as_tensor(np.asarray(tau_cell, dtype=np.float64).reshape(-1)
+                            if not isinstance(tau_cell, torch.Tensor) else tau_cell)
+        t = t.to(self.device, torch.float64).reshape(-1).contiguous()
+        if t.numel() != self.cells:
+            raise ValueError("tau field must have one value per cell")
+        check(_lib.lib().rlb_set_tau_field(self.h, _ptr(t)), "rlb_set_tau_field")
+        self.tau_cell = t
+
+    def hold_eta_over_s(self, eta_over_s: float, d_G: float = 16.0):
+        check(_lib.lib().rlb_hold_eta_over_s(self.h, float(eta_over_s), float(d_G)),
+              "rlb_hold_eta_over_s")
+
+    def transport(self, d_G: float = 16.0):
+        """(T, s, eta, eta/s) device float64 [cells] of the current state."""
+        out = [torch.empty(self.cells, dtype=torch.float64, device=self.device) for _ in range(4)]
+        check(_lib.lib().rlb_transport(self.h, float(d_G), *[_ptr(o) for o in out]),
+              "rlb_transport")
+        return tuple(out)
+
+    def adjoint_flush_tau_field(self, out: torch.Tensor):
+        check(_lib.lib().rlb_adjoint_flush_tau_field(self.h, _ptr(out)),
+              "rlb_adjoint_flush_tau_field")
 
     def state(self) -> torch.Tensor:
         """The buffer holding the current state, [2][bricks][19][64] (the buffer itself,

@@ -57,6 +57,9 @@ class Setup:
     e0: Optional[np.ndarray] = None  # [cells]
     beta0: Optional[np.ndarray] = None  # [3][cells]
     solid: Optional[np.ndarray] = None  # uint8 [cells]
+    tau_cell: Optional[np.ndarray] = None  # [cells]: per-cell relaxation times (else tau)
+    eta_s: float = 0.0  # > 0: hold eta/s fixed (tau from the local state)
+    d_G: float = 16.0  # degeneracy in n_eq = d_G T^3 / pi^2
 
     @property
     def cells(self) -> int:
