@@ -57,25 +57,30 @@ def lib():
             _build.build()
     L = ctypes.CDLL(path)
     L.ora_lattice.argtypes = [_ip, _dp, _ip]
-    L.ora_equilibria.argtypes = [ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double, _dp, _dp]
-    L.ora_invert.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp]
+    L.ora_equilibria.argtypes = [ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double,
+                                 ctypes.c_double, _dp, _dp]
+    L.ora_invert.argtypes = [ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double, _dp]
     L.ora_invert.restype = ctypes.c_int
-    L.ora_collide.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, _dp, _dp]
+    L.ora_collide.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp,
+                              _dp]
     L.ora_collide.restype = ctypes.c_int
     common = [_ip, ctypes.c_double, _ip, _dp, _u8p]
-    L.ora_init.argtypes = common + [_dp, _dp, _dp, _dp]
+    L.ora_init.argtypes = common + [ctypes.c_double, _dp, _dp, _dp, _dp]
     rxp = ctypes.POINTER(Relax)
     L.ora_run.argtypes = common + [rxp, _dp, ctypes.c_int]
     L.ora_run.restype = ctypes.c_long
     L.ora_run_g.argtypes = common + [rxp, _dp, ctypes.c_int]
     L.ora_run_g.restype = ctypes.c_long
     L.ora_update_cells.argtypes = common + [rxp, _dp, ctypes.c_long, _lp, _dp]
-    L.ora_moments.argtypes = [_ip, ctypes.c_double, _u8p, _dp, _dp, _dp, _dp, _dp]
+    L.ora_moments.argtypes = [_ip, ctypes.c_double, ctypes.c_double, _u8p, _dp, _dp, _dp, _dp,
+                              _dp]
     L.ora_adjoint_step.argtypes = common + [rxp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.ora_adjoint_step.restype = ctypes.c_int
     L.ora_transport.argtypes = [_ip, ctypes.c_double, _u8p, _dp, rxp, _dp, _dp, _dp, _dp]
-    L.ora_moments_adjoint.argtypes = [_ip, ctypes.c_double, _u8p, _dp, _dp, _dp, _dp]
-    L.ora_init_adjoint.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.ora_transport.restype = ctypes.c_int
+    L.ora_moments_adjoint.argtypes = [_ip, ctypes.c_double, ctypes.c_double, _u8p, _dp, _dp, _dp,
+                                      _dp]
+    L.ora_init_adjoint.argtypes = common + [ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.ora_loss.argtypes = common + [rxp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp]
     L.ora_loss.restype = ctypes.c_double
     L.ora_loss_cs.argtypes = common + [rxp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp,
@@ -105,7 +110,7 @@ class Relax(ctypes.Structure):
     """Relaxation source of a run (mirrors the oracle's OraRelax)."""
 
     _fields_ = [("tau", _dp), ("tau_cell", _dp), ("eta_s", ctypes.c_double),
-                ("d_G", ctypes.c_double)]
+                ("d_G", ctypes.c_double), ("kappa", ctypes.c_double)]
 
 
 @dataclass
@@ -124,6 +129,7 @@ class Problem:
     tau_cell: Optional[np.ndarray] = None  # [cells]: per-cell relaxation times
     eta_s: float = 0.0  # > 0: hold eta/s fixed (tau from the local state, f+g runs)
     d_G: float = 16.0  # degeneracy in n_eq = d_G T^3 / pi^2
+    kappa: float = 1.0 / 3.0  # equation of state P = kappa e
 
     @property
     def cells(self) -> int:
@@ -146,7 +152,7 @@ class Problem:
             tc = np.ascontiguousarray(np.asarray(self.tau_cell, dtype=np.float64).reshape(-1))
             assert tc.size == self.cells
         rx = Relax(tau.ctypes.data_as(_dp), tc.ctypes.data_as(_dp) if tc is not None else None,
-                   float(self.eta_s), float(self.d_G))
+                   float(self.eta_s), float(self.d_G), float(self.kappa))
         self._keep = (dims, bc, inflow, solid, tau, tc, rx)
         return (dims.ctypes.data_as(_ip), ctypes.c_double(self.c_l), bc.ctypes.data_as(_ip),
                 inflow.ctypes.data_as(_dp),
@@ -162,26 +168,28 @@ def lattice():
     return e, w, o
 
 
-def equilibria(n, eps, beta, c_l):
+def equilibria(n, eps, beta, c_l, kappa=1.0 / 3.0):
+    """(f^eq, g^eq); kappa = 1/3 uses eqs. equil1s/equil2as/equil2bs, any other
+    kappa eqs. equil1/equil2a/equil2b with P = kappa e."""
     feq = np.zeros(Q)
     geq = np.zeros(Q)
     b = _f64(beta)
-    lib().ora_equilibria(float(n), float(eps), _d(b), float(c_l), _d(feq), _d(geq))
+    lib().ora_equilibria(float(n), float(eps), _d(b), float(c_l), float(kappa), _d(feq), _d(geq))
     return feq, geq
 
 
-def invert(N, E, M):
+def invert(N, E, M, kappa=1.0 / 3.0):
     out = np.zeros(5)
     m = _f64(M)
-    ok = lib().ora_invert(float(N), float(E), _d(m), _d(out))
+    ok = lib().ora_invert(float(N), float(E), _d(m), float(kappa), _d(out))
     return out[0], out[1], out[2:5].copy(), bool(ok)
 
 
-def collide(pf, pg, tau, c_l):
+def collide(pf, pg, tau, c_l, kappa=1.0 / 3.0):
     pf, pg = _f64(pf), _f64(pg)
     of = np.zeros(Q)
     og = np.zeros(Q)
-    ok = lib().ora_collide(_d(pf), _d(pg), float(tau), float(c_l), _d(of), _d(og))
+    ok = lib().ora_collide(_d(pf), _d(pg), float(tau), float(c_l), float(kappa), _d(of), _d(og))
     return of, og, bool(ok)
 
 
@@ -190,12 +198,14 @@ def init(p: Problem, n0, e0, beta0) -> np.ndarray:
     args, _ = p._args()
     n0, e0, beta0 = _f64(n0).reshape(-1), _f64(e0).reshape(-1), _f64(beta0).reshape(3, -1)
     S = np.zeros((2, Q, p.cells))
-    lib().ora_init(*args, _d(n0), _d(e0), _d(np.ascontiguousarray(beta0)), _d(S))
+    lib().ora_init(*args, float(p.kappa), _d(n0), _d(e0), _d(np.ascontiguousarray(beta0)), _d(S))
     return S
 
 
 def run(p: Problem, S: np.ndarray, nsteps: int) -> int:
     """Advance S ([2][19][cells], in place) by nsteps; returns the unphysical-update count."""
+    if p.eta_s > 0 and p.kappa != 1.0 / 3.0:
+        raise ValueError("the eta/s rule is defined for e = 3P matter (kappa = 1/3)")
     args, rx = p._args()
     assert S.shape == (2, Q, p.cells) and S.dtype == np.float64 and S.flags.c_contiguous
     return int(lib().ora_run(*args, rx, _d(S), int(nsteps)))
@@ -227,7 +237,7 @@ def moments(p: Problem, S: np.ndarray):
     e = np.zeros(p.cells)
     b = np.zeros((3, p.cells))
     sums = np.zeros((p.batch, 5))
-    lib().ora_moments(dims.ctypes.data_as(_ip), float(p.c_l),
+    lib().ora_moments(dims.ctypes.data_as(_ip), float(p.c_l), float(p.kappa),
                       solid.ctypes.data_as(_u8p) if solid is not None else None,
                       _d(S), _d(n), _d(e), _d(b), _d(sums))
     return n, e, b, sums
@@ -257,7 +267,7 @@ def moments_adjoint(p: Problem, Sg, dLde, dLdb):
     solid = None if p.solid is None else np.ascontiguousarray(p.solid.reshape(-1).astype(np.uint8))
     Sg, dLde, dLdb = _f64(Sg), _f64(dLde).reshape(-1), _f64(dLdb).reshape(3, -1)
     lam = np.zeros((Q, p.cells))
-    lib().ora_moments_adjoint(dims.ctypes.data_as(_ip), float(p.c_l),
+    lib().ora_moments_adjoint(dims.ctypes.data_as(_ip), float(p.c_l), float(p.kappa),
                               solid.ctypes.data_as(_u8p) if solid is not None else None,
                               _d(Sg), _d(dLde), _d(np.ascontiguousarray(dLdb)), _d(lam))
     return lam
@@ -270,7 +280,8 @@ def init_adjoint(p: Problem, e0, beta0, lam0):
     db0 = np.zeros((3, p.cells))
     dbin = np.zeros(3)
     dein = np.zeros(1)
-    lib().ora_init_adjoint(*args, _d(e0), _d(np.ascontiguousarray(beta0)), _d(lam0), _d(de0),
+    lib().ora_init_adjoint(*args, float(p.kappa), _d(e0), _d(np.ascontiguousarray(beta0)),
+                           _d(lam0), _d(de0),
                            _d(db0), _d(dbin), _d(dein))
     return de0, db0, dbin, dein[0]
 
@@ -350,7 +361,9 @@ def transport(p: Problem, S: np.ndarray):
     _, rx = p._args()
     solid = None if p.solid is None else np.ascontiguousarray(p.solid.reshape(-1).astype(np.uint8))
     out = [np.zeros(p.cells) for _ in range(4)]
-    lib().ora_transport(dims.ctypes.data_as(_ip), float(p.c_l),
-                        solid.ctypes.data_as(_u8p) if solid is not None else None, _d(S), rx,
-                        *[_d(o) for o in out])
+    ok = lib().ora_transport(dims.ctypes.data_as(_ip), float(p.c_l),
+                             solid.ctypes.data_as(_u8p) if solid is not None else None, _d(S),
+                             rx, *[_d(o) for o in out])
+    if not ok:
+        raise ValueError("transport quantities are defined for e = 3P matter (kappa = 1/3)")
     return tuple(out)

@@ -22,6 +22,8 @@
 //   * BGK update with one tau for both populations: eqs. (lbe1), (lbe2).
 //   * ultra-relativistic equilibria: eqs. (equil1s), (equil2as), (equil2bs),
 //     written literally with gamma^2 = 1/(1 - |beta|^2) and c = 1.
+//   * general equation of state: eqs. (equil1), (equil2a), (equil2b) with
+//     P = kappa e (kappa = 1/3 selects the ultra-relativistic forms above).
 //
 //   * shear viscosity of the model, eta = (4/9) gamma^2 e (tau - dt/2) c_l^2
 //     (end of the equilibrium section), and the transport quantities of the
@@ -94,6 +96,7 @@ struct Lattice {
   int n[3];  // extents along x, y, z
   int batch;
   double c_l;
+  double kappa;  // equation of state P = kappa e
   int bc[3][2];
   long cells() const { return (long)batch * n[0] * n[1] * n[2]; }
   long index(int b, int x, int y, int z) const {
@@ -123,6 +126,7 @@ Lattice make_lattice(const int32_t *dims, double c_l, const int32_t *bc) {
   L.n[2] = dims[2];
   L.batch = dims[3];
   L.c_l = c_l;
+  L.kappa = 1.0 / 3.0;
   for (int a = 0; a < 3; ++a)
     for (int s = 0; s < 2; ++s) L.bc[a][s] = bc[2 * a + s];
   return L;
@@ -192,19 +196,82 @@ bool invert(T N, T E, const T M[3], T *n, T *eps, T beta[3]) {
   return ok;
 }
 
+// General-EoS equilibria, eqs. (equil1), (equil2a), (equil2b), literally, with
+// the pressure P given alongside e.
+template <class T>
+void equilibria_eos(T n, T eps, T P, const T beta[3], double c_l, T feq[Q], T geq[Q]) {
+  using std::sqrt;
+  T u2 = beta[0] * beta[0] + beta[1] * beta[1] + beta[2] * beta[2];
+  T gamma2 = 1.0 / (1.0 - u2);
+  T gamma = sqrt(gamma2);
+  double cl2 = c_l * c_l;
+  for (int q = 0; q < Q; ++q) {
+    double w = weight(q);
+    double c[3] = {c_l * EV[q][0], c_l * EV[q][1], c_l * EV[q][2]};
+    T cu = c[0] * beta[0] + c[1] * beta[1] + c[2] * beta[2];
+    feq[q] = w * n * gamma * (1.0 + 3.0 * cu / cl2);
+    if (q > 0)
+      geq[q] = w * (eps + P) * gamma2 *
+               (3.0 * P / ((P + eps) * gamma2 * cl2) + 3.0 * cu / cl2 +
+                4.5 * cu * cu / (cl2 * cl2) - 1.5 * u2 / cl2);
+    else
+      geq[q] = w * (eps + P) * gamma2 *
+               (3.0 - 3.0 * P * (2.0 + cl2) / ((P + eps) * gamma2 * cl2) - 1.5 * u2 / cl2);
+  }
+}
+
+// Inversion of the constraints for P = kappa e.  With W = (e+P) gamma^2 the
+// constraints read E = W - P, M = W beta, and |beta|^2 = 1 - 1/gamma^2 gives
+// W^2 - (1 + kappa) E W + kappa |M|^2 = 0; the root continuous with rest
+// (W = (1 + kappa) E at M = 0) is taken, then beta = M / W,
+// e = W / ((1 + kappa) gamma^2), n = N / gamma.
+template <class T>
+bool invert_eos(T N, T E, const T M[3], double kappa, T *n, T *eps, T beta[3]) {
+  using std::sqrt;
+  T M2 = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  T disc = (1.0 + kappa) * (1.0 + kappa) * E * E - 4.0 * kappa * M2;
+  T W = ((1.0 + kappa) * E + sqrt(disc)) / 2.0;
+  for (int a = 0; a < 3; ++a) beta[a] = M[a] / W;
+  T b2 = beta[0] * beta[0] + beta[1] * beta[1] + beta[2] * beta[2];
+  T gamma2 = 1.0 / (1.0 - b2);
+  *eps = W / ((1.0 + kappa) * gamma2);
+  *n = N / sqrt(gamma2);
+  return re(disc) > 0.0 && re(*eps) > 0.0 && re(b2) < 1.0;
+}
+
+// Dispatch on the equation of state: kappa = 1/3 takes the ultra-relativistic
+// forms (equil1s/equil2as/equil2bs and the e = 3P inversion), any other kappa
+// the general ones.
+inline bool radiation(double kappa) { return kappa == 1.0 / 3.0; }
+
+template <class T>
+void eq_any(T n, T eps, const T beta[3], double c_l, double kappa, T feq[Q], T geq[Q]) {
+  if (radiation(kappa))
+    equilibria(n, eps, beta, c_l, feq, geq);
+  else
+    equilibria_eos(n, eps, T(kappa * eps), beta, c_l, feq, geq);
+}
+
+template <class T>
+bool inv_any(T N, T E, const T M[3], double kappa, T *n, T *eps, T beta[3]) {
+  if (radiation(kappa)) return invert(N, E, M, n, eps, beta);
+  return invert_eos(N, E, M, kappa, n, eps, beta);
+}
+
 // One BGK collision, eqs. (lbe1)/(lbe2): post = pre - (dt/tau)(pre - eq), with
 // tau given in units of dt.  With do_f false the f population is skipped (its
 // outputs are left untouched): f never enters (e, beta).
 template <class T>
-bool collide(const T pf[Q], const T pg[Q], T tau, double c_l, bool do_f, T of[Q], T og[Q]) {
+bool collide(const T pf[Q], const T pg[Q], T tau, double c_l, bool do_f, T of[Q], T og[Q],
+             double kappa = 1.0 / 3.0) {
   T N, E, M[3];
   T zero[Q];
   for (int q = 0; q < Q; ++q) zero[q] = 0.0;
   moment_sums(do_f ? pf : zero, pg, c_l, &N, &E, M);
   T n, eps, beta[3];
-  bool ok = invert(N, E, M, &n, &eps, beta);
+  bool ok = inv_any(N, E, M, kappa, &n, &eps, beta);
   T feq[Q], geq[Q];
-  equilibria(n, eps, beta, c_l, feq, geq);
+  eq_any(n, eps, beta, c_l, kappa, feq, geq);
   for (int q = 0; q < Q; ++q) {
     og[q] = pg[q] - (1.0 / tau) * (pg[q] - geq[q]);
     if (do_f) of[q] = pf[q] - (1.0 / tau) * (pf[q] - feq[q]);
@@ -314,7 +381,7 @@ long step(const Lattice &L, const Relax<T> &rx, const uint8_t *solid, const T in
           }
           T tau = rx.tau_cell ? rx.tau_cell[i] : rx.tau[b];
           if (rx.eta_s > 0.0) tau = tau_for_eta_s(pf, pg, L.c_l, rx.eta_s, rx.d_G);
-          if (!collide(pf, pg, tau, L.c_l, do_f, of, og)) ++unphysical;
+          if (!collide(pf, pg, tau, L.c_l, do_f, of, og, L.kappa)) ++unphysical;
           for (int q = 0; q < Q; ++q) {
             gout[(long)q * C + i] = og[q];
             if (do_f) fout[(long)q * C + i] = of[q];
@@ -325,7 +392,7 @@ long step(const Lattice &L, const Relax<T> &rx, const uint8_t *solid, const T in
 
 template <class T>
 void inflow_equilibria(const Lattice &L, T in_n, T in_e, const T in_b[3], T in_f[Q], T in_g[Q]) {
-  equilibria(in_n, in_e, in_b, L.c_l, in_f, in_g);
+  eq_any(in_n, in_e, in_b, L.c_l, L.kappa, in_f, in_g);
 }
 
 // S_0: equilibrium of the initial fields; inflow cells take the inflow state;
@@ -352,7 +419,7 @@ void init_state(const Lattice &L, const uint8_t *solid, const T *n0, const T *e0
           } else {
             T beta[3] = {beta0[i], beta0[C + i], beta0[2 * C + i]};
             T n = do_f ? n0[i] : T(1.0);
-            equilibria(n, e0[i], beta, L.c_l, feq, geq);
+            eq_any(n, e0[i], beta, L.c_l, L.kappa, feq, geq);
           }
           for (int q = 0; q < Q; ++q) {
             g[(long)q * C + i] = geq[q];
@@ -380,7 +447,7 @@ void fields(const Lattice &L, const uint8_t *solid, const T *S, bool do_f, T *n,
     }
     T N, E, M[3], nn, ee, bb[3];
     moment_sums(pf, pg, L.c_l, &N, &E, M);
-    invert(N, E, M, &nn, &ee, bb);
+    inv_any(N, E, M, L.kappa, &nn, &ee, bb);
     if (n) n[i] = nn;
     e[i] = ee;
     beta[i] = bb[0];
@@ -415,36 +482,37 @@ T loss_value(const Lattice &L, const uint8_t *solid, const T *e, const T *beta, 
 
 // Complex-step derivative of the g-collision output with respect to every
 // input of one cell: J[q][p] = d post_q / d pre_p, and d post_q / d tau.
-void collide_jacobian(const double pg[Q], double tau, double c_l, double J[Q][Q], double dtau[Q]) {
+void collide_jacobian(const double pg[Q], double tau, double c_l, double kappa, double J[Q][Q],
+                      double dtau[Q]) {
   const double h = 1e-30;
   cplx zf[Q], of[Q], og[Q], cg[Q];
   for (int q = 0; q < Q; ++q) zf[q] = 0.0;
   for (int p = 0; p < Q; ++p) {
     for (int q = 0; q < Q; ++q) cg[q] = cplx(pg[q], q == p ? h : 0.0);
-    collide<cplx>(zf, cg, cplx(tau, 0.0), c_l, false, of, og);
+    collide<cplx>(zf, cg, cplx(tau, 0.0), c_l, false, of, og, kappa);
     for (int q = 0; q < Q; ++q) J[q][p] = og[q].imag() / h;
   }
   for (int q = 0; q < Q; ++q) cg[q] = cplx(pg[q], 0.0);
-  collide<cplx>(zf, cg, cplx(tau, h), c_l, false, of, og);
+  collide<cplx>(zf, cg, cplx(tau, h), c_l, false, of, og, kappa);
   for (int q = 0; q < Q; ++q) dtau[q] = og[q].imag() / h;
 }
 
 // d g^eq_q / d(e, beta_0, beta_1, beta_2) at (e, beta) by complex step.
-void geq_jacobian(double e, const double beta[3], double c_l, double J[Q][4]) {
+void geq_jacobian(double e, const double beta[3], double c_l, double kappa, double J[Q][4]) {
   const double h = 1e-30;
   cplx feq[Q], geq[Q];
   for (int k = 0; k < 4; ++k) {
     cplx ce(e, k == 0 ? h : 0.0);
     cplx cb[3] = {cplx(beta[0], k == 1 ? h : 0.0), cplx(beta[1], k == 2 ? h : 0.0),
                   cplx(beta[2], k == 3 ? h : 0.0)};
-    equilibria<cplx>(cplx(1.0, 0.0), ce, cb, c_l, feq, geq);
+    eq_any<cplx>(cplx(1.0, 0.0), ce, cb, c_l, kappa, feq, geq);
     for (int q = 0; q < Q; ++q) J[q][k] = geq[q].imag() / h;
   }
 }
 
 // d(e, beta_0, beta_1, beta_2) / d g_p of one stored cell, by complex step on
 // the moment inversion.
-void fields_jacobian(const double g[Q], double c_l, double J[4][Q]) {
+void fields_jacobian(const double g[Q], double c_l, double kappa, double J[4][Q]) {
   const double h = 1e-30;
   cplx cf[Q], cg[Q];
   for (int q = 0; q < Q; ++q) cf[q] = 0.0;
@@ -452,7 +520,7 @@ void fields_jacobian(const double g[Q], double c_l, double J[4][Q]) {
     for (int q = 0; q < Q; ++q) cg[q] = cplx(g[q], q == p ? h : 0.0);
     cplx N, E, M[3], n, e, b[3];
     moment_sums(cf, cg, c_l, &N, &E, M);
-    invert(N, E, M, &n, &e, b);
+    inv_any(N, E, M, kappa, &n, &e, b);
     J[0][p] = e.imag() / h;
     for (int k = 0; k < 3; ++k) J[1 + k][p] = b[k].imag() / h;
   }
@@ -471,7 +539,7 @@ void adjoint_step_g(const Lattice &L, const Relax<double> &rx, const uint8_t *so
   const long C = L.cells();
   for (long k = 0; k < (long)Q * C; ++k) lam_out[k] = 0.0;
   double Jin[Q][4];
-  geq_jacobian(in_e, in_b, L.c_l, Jin);
+  geq_jacobian(in_e, in_b, L.c_l, L.kappa, Jin);
   for (int b = 0; b < L.batch; ++b)
     for (int z = 0; z < L.n[2]; ++z)
       for (int y = 0; y < L.n[1]; ++y)
@@ -496,7 +564,7 @@ void adjoint_step_g(const Lattice &L, const Relax<double> &rx, const uint8_t *so
             pg[q] = Sg[(long)src[q].q * C + src[q].idx];
           }
           double J[Q][Q], dt[Q];
-          collide_jacobian(pg, rx.tau_cell ? rx.tau_cell[i] : rx.tau[b], L.c_l, J, dt);
+          collide_jacobian(pg, rx.tau_cell ? rx.tau_cell[i] : rx.tau[b], L.c_l, L.kappa, J, dt);
           for (int p = 0; p < Q; ++p) {
             double mu = 0.0;
             for (int q = 0; q < Q; ++q) mu += lam[q] * J[q][p];
@@ -522,7 +590,7 @@ void moments_adjoint_g(const Lattice &L, const uint8_t *solid, const double *Sg,
     }
     double g[Q], J[4][Q];
     for (int q = 0; q < Q; ++q) g[q] = Sg[(long)q * C + i];
-    fields_jacobian(g, L.c_l, J);
+    fields_jacobian(g, L.c_l, L.kappa, J);
     for (int p = 0; p < Q; ++p) {
       double v = dLde[i] * J[0][p];
       for (int k = 0; k < 3; ++k) v += dLdb[k * C + i] * J[1 + k][p];
@@ -538,7 +606,7 @@ void init_adjoint_g(const Lattice &L, const uint8_t *solid, const double *e0, co
                     double *dLdb0, double *dbeta_in, double *de_in) {
   const long C = L.cells();
   double Jin[Q][4];
-  geq_jacobian(in_e, in_b, L.c_l, Jin);
+  geq_jacobian(in_e, in_b, L.c_l, L.kappa, Jin);
   for (int b = 0; b < L.batch; ++b)
     for (int z = 0; z < L.n[2]; ++z)
       for (int y = 0; y < L.n[1]; ++y)
@@ -559,7 +627,7 @@ void init_adjoint_g(const Lattice &L, const uint8_t *solid, const double *e0, co
           }
           double bt[3] = {beta0[i], beta0[C + i], beta0[2 * C + i]};
           double J[Q][4];
-          geq_jacobian(e0[i], bt, L.c_l, J);
+          geq_jacobian(e0[i], bt, L.c_l, L.kappa, J);
           double s[4] = {0, 0, 0, 0};
           for (int q = 0; q < Q; ++q) {
             double l = lam[(long)q * C + i];
@@ -582,14 +650,18 @@ Relax<double> relax_of(const void *r);
 // 2 inflow); inflow = {n, e, beta_x, beta_y, beta_z}.
 extern "C" {
 
-// Relaxation source of a run: tau[batch]; optional tau_cell[cells]; eta_s > 0
-// holds eta/s fixed with degeneracy d_G (f+g runs only).
+// Parameters of a run: tau[batch]; optional tau_cell[cells]; eta_s > 0 holds
+// eta/s fixed with degeneracy d_G (f+g runs only); kappa: P = kappa e
+// (0 means 1/3, the paper's e = 3P).
 struct OraRelax {
   const double *tau;
   const double *tau_cell;
   double eta_s;
   double d_G;
+  double kappa;
 };
+
+static double kappa_of(double k) { return k == 0.0 ? 1.0 / 3.0 : k; }
 
 int ora_num_directions() { return Q; }
 
@@ -601,14 +673,15 @@ void ora_lattice(int32_t *e /*[19][3]*/, double *w /*[19]*/, int32_t *opp /*[19]
   }
 }
 
-void ora_equilibria(double n, double eps, const double *beta, double c_l, double *feq,
-                    double *geq) {
-  equilibria<double>(n, eps, beta, c_l, feq, geq);
+void ora_equilibria(double n, double eps, const double *beta, double c_l, double kappa,
+                    double *feq, double *geq) {
+  eq_any<double>(n, eps, beta, c_l, kappa_of(kappa), feq, geq);
 }
 
-int ora_invert(double N, double E, const double *M, double *out /* n, e, bx, by, bz */) {
+int ora_invert(double N, double E, const double *M, double kappa,
+               double *out /* n, e, bx, by, bz */) {
   double n, e, b[3];
-  bool ok = invert<double>(N, E, M, &n, &e, b);
+  bool ok = inv_any<double>(N, E, M, kappa_of(kappa), &n, &e, b);
   out[0] = n;
   out[1] = e;
   out[2] = b[0];
@@ -617,15 +690,16 @@ int ora_invert(double N, double E, const double *M, double *out /* n, e, bx, by,
   return ok ? 1 : 0;
 }
 
-int ora_collide(const double *pf, const double *pg, double tau, double c_l, double *of,
-                double *og) {
-  return collide<double>(pf, pg, tau, c_l, true, of, og) ? 1 : 0;
+int ora_collide(const double *pf, const double *pg, double tau, double c_l, double kappa,
+                double *of, double *og) {
+  return collide<double>(pf, pg, tau, c_l, true, of, og, kappa_of(kappa)) ? 1 : 0;
 }
 
 void ora_init(const int32_t *dims, double c_l, const int32_t *bc, const double *inflow,
-              const uint8_t *solid, const double *n0, const double *e0, const double *beta0,
-              double *S) {
+              const uint8_t *solid, double kappa, const double *n0, const double *e0,
+              const double *beta0, double *S) {
   Lattice L = make_lattice(dims, c_l, bc);
+  L.kappa = kappa_of(kappa);
   double in_f[Q], in_g[Q];
   inflow_equilibria<double>(L, inflow[0], inflow[1], inflow + 2, in_f, in_g);
   init_state<double>(L, solid, n0, e0, beta0, in_f, in_g, S, true);
@@ -637,6 +711,8 @@ long ora_run(const int32_t *dims, double c_l, const int32_t *bc, const double *i
              const uint8_t *solid, const OraRelax *rxp, double *S, int nsteps) {
   const Relax<double> rx = relax_of(rxp);
   Lattice L = make_lattice(dims, c_l, bc);
+  L.kappa = kappa_of(rxp->kappa);
+  if (rx.eta_s > 0.0 && !radiation(L.kappa)) return -1;  // the eta/s rule is for e = 3P
   double in_f[Q], in_g[Q];
   inflow_equilibria<double>(L, inflow[0], inflow[1], inflow + 2, in_f, in_g);
   const long n = 2L * Q * L.cells();
@@ -657,6 +733,7 @@ long ora_run_g(const int32_t *dims, double c_l, const int32_t *bc, const double 
   const Relax<double> rx = relax_of(rxp);
   if (rx.eta_s > 0.0) return -1;  // holding eta/s needs n, i.e. the f population
   Lattice L = make_lattice(dims, c_l, bc);
+  L.kappa = kappa_of(rxp->kappa);
   double in_f[Q], in_g[Q];
   inflow_equilibria<double>(L, inflow[0], inflow[1], inflow + 2, in_f, in_g);
   const long n = (long)Q * L.cells();
@@ -678,6 +755,7 @@ void ora_update_cells(const int32_t *dims, double c_l, const int32_t *bc, const 
                       const long *idx, double *out) {
   const Relax<double> rx = relax_of(rxp);
   Lattice L = make_lattice(dims, c_l, bc);
+  L.kappa = kappa_of(rxp->kappa);
   double in_f[Q], in_g[Q];
   inflow_equilibria<double>(L, inflow[0], inflow[1], inflow + 2, in_f, in_g);
   const long C = L.cells();
@@ -719,10 +797,11 @@ void ora_update_cells(const int32_t *dims, double c_l, const int32_t *bc, const 
 // Fields (n, e, beta[3][cells]) and per-instance conservation sums
 // sums[b][5] = (sum f, sum g, sum g c_x, sum g c_y, sum g c_z) over non-solid
 // cells.
-void ora_moments(const int32_t *dims, double c_l, const uint8_t *solid, const double *S,
-                 double *n, double *e, double *beta, double *sums) {
+void ora_moments(const int32_t *dims, double c_l, double kappa, const uint8_t *solid,
+                 const double *S, double *n, double *e, double *beta, double *sums) {
   int32_t bc0[6] = {0, 0, 0, 0, 0, 0};
   Lattice L = make_lattice(dims, c_l, bc0);
+  L.kappa = kappa_of(kappa);
   fields<double>(L, solid, S, true, n, e, beta);
   if (!sums) return;
   const long C = L.cells();
@@ -753,23 +832,26 @@ int ora_adjoint_step(const int32_t *dims, double c_l, const int32_t *bc, const d
   const Relax<double> rx = relax_of(rxp);
   if (rx.eta_s > 0.0) return 0;  // g-only reverse mode does not hold with tau(n)
   Lattice L = make_lattice(dims, c_l, bc);
+  L.kappa = kappa_of(rxp->kappa);
   adjoint_step_g(L, rx, solid, inflow[1], inflow + 2, Sg, lam_next, lam_out, dtau, dbeta_in,
                  de_in, dtau_cell);
   return 1;
 }
 
-void ora_moments_adjoint(const int32_t *dims, double c_l, const uint8_t *solid, const double *Sg,
-                         const double *dLde, const double *dLdb, double *lam) {
+void ora_moments_adjoint(const int32_t *dims, double c_l, double kappa, const uint8_t *solid,
+                         const double *Sg, const double *dLde, const double *dLdb, double *lam) {
   int32_t bc0[6] = {0, 0, 0, 0, 0, 0};
   Lattice L = make_lattice(dims, c_l, bc0);
+  L.kappa = kappa_of(kappa);
   moments_adjoint_g(L, solid, Sg, dLde, dLdb, lam);
 }
 
 void ora_init_adjoint(const int32_t *dims, double c_l, const int32_t *bc, const double *inflow,
-                      const uint8_t *solid, const double *e0, const double *beta0,
+                      const uint8_t *solid, double kappa, const double *e0, const double *beta0,
                       const double *lam, double *dLde0, double *dLdb0, double *dbeta_in,
                       double *de_in) {
   Lattice L = make_lattice(dims, c_l, bc);
+  L.kappa = kappa_of(kappa);
   init_adjoint_g(L, solid, e0, beta0, inflow[1], inflow + 2, lam, dLde0, dLdb0, dbeta_in, de_in);
 }
 
@@ -780,6 +862,7 @@ double ora_loss(const int32_t *dims, double c_l, const int32_t *bc, const double
                 const double *lbb) {
   const Relax<double> rx = relax_of(rxp);
   Lattice L = make_lattice(dims, c_l, bc);
+  L.kappa = kappa_of(rxp->kappa);
   const long C = L.cells();
   double in_f[Q], in_g[Q];
   inflow_equilibria<double>(L, inflow[0], inflow[1], inflow + 2, in_f, in_g);
@@ -808,6 +891,7 @@ double ora_loss_cs(const int32_t *dims, double c_l, const int32_t *bc, const dou
                    const double *d_tau_cell, double *loss) {
   const double h = 1e-30;
   Lattice L = make_lattice(dims, c_l, bc);
+  L.kappa = kappa_of(rxp->kappa);
   const long C = L.cells();
   const double *tau = rxp->tau;
   std::vector<cplx> ctau(L.batch), ce0(C), cb0(3 * C), ctc;
@@ -850,6 +934,7 @@ double ora_gradient(const int32_t *dims, double c_l, const int32_t *bc, const do
                     double *g_e0, double *g_beta0, double *g_tau_cell) {
   const Relax<double> rx = relax_of(rxp);
   Lattice L = make_lattice(dims, c_l, bc);
+  L.kappa = kappa_of(rxp->kappa);
   const long C = L.cells();
   const long QC = (long)Q * C;
   double in_f[Q], in_g[Q];
@@ -893,11 +978,13 @@ double ora_gradient(const int32_t *dims, double c_l, const int32_t *bc, const do
 // cells): temperature, entropy density, shear viscosity and eta/s, with each
 // cell's relaxation time from the relaxation source (for eta_s > 0 the tau
 // that the rule gives at the cell's own fields).
-void ora_transport(const int32_t *dims, double c_l, const uint8_t *solid, const double *S,
-                   const OraRelax *rxp, double *temp, double *s, double *eta, double *eta_over_s) {
+int ora_transport(const int32_t *dims, double c_l, const uint8_t *solid, const double *S,
+                  const OraRelax *rxp, double *temp, double *s, double *eta, double *eta_over_s) {
   const Relax<double> rx = relax_of(rxp);
   int32_t bc0[6] = {0, 0, 0, 0, 0, 0};
   Lattice L = make_lattice(dims, c_l, bc0);
+  L.kappa = kappa_of(rxp->kappa);
+  if (!radiation(L.kappa)) return 0;  // T = e/(3n) and n_eq are those of e = 3P matter
   const long C = L.cells();
   const long per = (long)L.n[0] * L.n[1] * L.n[2];
   for (long i = 0; i < C; ++i) {
@@ -916,6 +1003,7 @@ void ora_transport(const int32_t *dims, double c_l, const uint8_t *solid, const 
     transport(n, eps, beta, tau, c_l, rx.d_G, &temp[i], &s[i], &eta[i]);
     eta_over_s[i] = eta[i] / s[i];
   }
+  return 1;
 }
 
 }  // extern "C"

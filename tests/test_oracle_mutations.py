@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "rlb_oracle.cpp")
 PINS = [os.path.join(ROOT, "tests", f) for f in
         ("test_oracle_pins.py", "test_oracle_riemann.py", "test_oracle_gradients.py",
-         "test_oracle_transport.py")]
+         "test_oracle_transport.py", "test_oracle_eos.py")]
 
 MUTATIONS = {
     "drop_quadratic_term": ("6.0 * cu * cu / (cl2 * cl2)", "0.0 * cu * cu / (cl2 * cl2)"),
@@ -46,6 +46,13 @@ MUTATIONS = {
     "eta_s_rule_uses_n": ("T eta = eta_s * s;", "T eta = eta_s * n;"),
     "tau_cell_gradient_overwritten": ("if (dtau_cell) dtau_cell[i] += s;",
                                       "if (dtau_cell) dtau_cell[i] = s;"),
+    "eos_pressure_term": ("(3.0 * P / ((P + eps) * gamma2 * cl2)",
+                          "(2.0 * P / ((P + eps) * gamma2 * cl2)"),
+    "eos_rest_coefficient": ("3.0 * P * (2.0 + cl2)", "3.0 * P * (1.0 + cl2)"),
+    "eos_root_sign": ("T W = ((1.0 + kappa) * E + sqrt(disc)) / 2.0;",
+                      "T W = ((1.0 + kappa) * E - sqrt(disc)) / 2.0;"),
+    "eos_energy_from_W": ("*eps = W / ((1.0 + kappa) * gamma2);",
+                          "*eps = W / ((1.0 + kappa) * gamma2 * gamma2);"),
 }
 
 
