@@ -92,6 +92,8 @@ typedef struct {
   int32_t storage;           /* rlb_storage                                      */
   double n_ref, e_ref;       /* rest reference of the *DEV storages              */
   int32_t collide;           /* rlb_collide                                      */
+  double kappa;              /* equation of state P = kappa e, 0 < kappa <= 1;   */
+                             /* 0 selects 1/3 (e = 3P, the paper's simulations)  */
 } rlb_params;
 
 /* Layout of one population buffer for these parameters: q_stride (cells

@@ -38,6 +38,7 @@ class Params(ctypes.Structure):
         ("storage", ctypes.c_int32),
         ("n_ref", ctypes.c_double), ("e_ref", ctypes.c_double),
         ("collide", ctypes.c_int32),
+        ("kappa", ctypes.c_double),
     ]
 
 

@@ -86,7 +86,12 @@ __device__ __forceinline__ size_t at(int q, long long i) {
 }
 
 struct Phys {
-  double c, inv_c, inv_c2, k0;  // k0 = 3 - 2/c_l^2
+  double c, inv_c, inv_c2, k0;  // k0 = 3 - 6 kappa / c_l^2 (3 - 2/c_l^2 for e = 3P)
+  double ad_c;                  // 3 kappa / c_l^2 (1/c_l^2 for e = 3P)
+  double wfac;                  // W = wfac e gamma^2, wfac = 1 + kappa
+  double kappa;                 // P = kappa e
+  int gen_eos;                  // kappa != 1/3
+  double eos_A, eos_B, eos_C, eos_H, eos_F, eos_G;  // inversion constants (see invert)
   double n_ref, e_ref;          // zero unless the storage holds deviations
   const double *omega;          // [batch] 1/tau
   const uint8_t *cls;           // [cells] class bits, or null (no obstacle)
@@ -283,16 +288,21 @@ struct Inv {
   bool bad;
 };
 
-__device__ __forceinline__ Inv invert(double E, double Mx, double My, double Mz) {
+__device__ __forceinline__ Inv invert(const Phys &ph, double E, double Mx, double My, double Mz) {
   Inv r;
   r.E = E;
   r.Mx = Mx;
   r.My = My;
   r.Mz = Mz;
-  double D2 = 4.0 * E * E - 3.0 * (Mx * Mx + My * My + Mz * Mz);
+  // W^2 - (1 + kappa) E W + kappa |M|^2 = 0 (from E = W - P, |M| = W |beta|,
+  // P = kappa e), rest-continuous root, as D^2 = A E^2 - B |M|^2,
+  // W = (C E + D) H, e = (D - F E) G.  For kappa = 1/3 the constants are
+  // (4, 3, 2, 1/3, 1, 1): D = sqrt(4E^2 - 3|M|^2), W = (2E + D)/3, e = D - E;
+  // otherwise ((1+kappa)^2, 4 kappa, 1 + kappa, 1/2, 1 - kappa, 1/(2 kappa)).
+  const double D2 = ph.eos_A * E * E - ph.eos_B * (Mx * Mx + My * My + Mz * Mz);
   r.D = sqrt(D2);
-  r.eps = r.D - E;
-  r.W = (2.0 * E + r.D) * (1.0 / 3.0);
+  r.eps = (r.D - ph.eos_F * E) * ph.eos_G;
+  r.W = (ph.eos_C * E + r.D) * ph.eos_H;
   double iW = 1.0 / r.W;
   r.bx = Mx * iW;
   r.by = My * iW;
@@ -317,7 +327,7 @@ __device__ __forceinline__ EqCoef<T> eq_coef(const Phys &ph, double N, double ep
   double b2 = bx * bx + by * by + bz * bz;
   double s = 1.5 * b2 * ph.inv_c2;
   k.W = (T)W;
-  k.Ad = (T)((eps - ph.e_ref) * ph.inv_c2);
+  k.Ad = (T)((eps - ph.e_ref) * ph.ad_c);
   k.A0 = (T)((eps - ph.e_ref) * ph.k0 + W * (3.0 * b2 - s));
   k.bx = (T)(bx * ph.inv_c);
   k.by = (T)(by * ph.inv_c);
@@ -357,7 +367,7 @@ __device__ __forceinline__ T feq_dev(const EqCoef<T> &k, int q) {
 
 // Rest reference R_q (deviation storage) in FP64.
 __device__ __forceinline__ double rest_g(const Phys &ph, int q) {
-  return q == 0 ? W0 * ph.e_ref * ph.k0 : WQ[q] * ph.e_ref * ph.inv_c2;
+  return q == 0 ? W0 * ph.e_ref * ph.k0 : WQ[q] * ph.e_ref * ph.ad_c;
 }
 __device__ __forceinline__ double rest_f(const Phys &ph, int q) { return WQ[q] * ph.n_ref; }
 
@@ -490,7 +500,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
 #pragma unroll
   for (int q = 0; q < Q; ++q) sE += pg[q];
   mirror_sums(pg, sx, sy, sz);
-  const Inv iv = invert(ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
+  const Inv iv = invert(ph, ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
                         ph.c * (double)sz);
   EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
   double omd = omega_of(ph, c.b, c.idx);
@@ -571,7 +581,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(const Geom g, const Phys ph,
   const double g2 = 1.0 / (1.0 - (bx * bx + by * by + bz * bz));
   const double e = e0[c.idx];
   const double N = n0[c.idx] * sqrt(g2);
-  const EqCoef<T> k = eq_coef<T>(ph, N, e, (4.0 / 3.0) * e * g2, bx, by, bz);
+  const EqCoef<T> k = eq_coef<T>(ph, N, e, ph.wfac * e * g2, bx, by, bz);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     pa[at(q, c.idx)] = Cd::enc(feq_dev(k, q));
@@ -587,7 +597,7 @@ __global__ void k_inflow_eq(const Phys ph, double n, double e, double bx, double
   using T = typename Cd::calc;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const double g2 = 1.0 / (1.0 - (bx * bx + by * by + bz * bz));
-  const EqCoef<T> k = eq_coef<T>(ph, n * sqrt(g2), e, (4.0 / 3.0) * e * g2, bx, by, bz);
+  const EqCoef<T> k = eq_coef<T>(ph, n * sqrt(g2), e, ph.wfac * e * g2, bx, by, bz);
   for (int q = 0; q < Q; ++q) {
     out[q] = Cd::enc(feq_dev(k, q));
     out[Q + q] = Cd::enc(geq_dev(k, q));
@@ -624,7 +634,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const Geom g, const Phys ph,
       mirror_sums(gv, sx, sy, sz);
       if (Sf) N += ph.n_ref;  // the rest parts sum to (n_ref, e_ref, 0)
       Eg += ph.e_ref;
-      const Inv iv = invert(Eg, ph.c * sx, ph.c * sy, ph.c * sz);
+      const Inv iv = invert(ph, Eg, ph.c * sx, ph.c * sy, ph.c * sz);
       if (n && Sf) n[c.idx] = N * sqrt(1.0 - (iv.bx * iv.bx + iv.by * iv.by + iv.bz * iv.bz));
       if (e) e[c.idx] = iv.eps;
       if (beta) {
@@ -670,7 +680,7 @@ __global__ __launch_bounds__(BLOCK) void k_transport(const Geom g, const Phys ph
       Eg += gv[q];
     }
     mirror_sums(gv, sx, sy, sz);
-    const Inv iv = invert(Eg, ph.c * sx, ph.c * sy, ph.c * sz);
+    const Inv iv = invert(ph, Eg, ph.c * sx, ph.c * sy, ph.c * sz);
     const double b2 = iv.bx * iv.bx + iv.by * iv.by + iv.bz * iv.bz;
     const double n = N * sqrt(1.0 - b2);
     const double om = ph.eta_s > 0.0 ? omega_for_eta_s(ph, n, iv.eps, b2) : omega_of(ph, c.b, c.idx);
@@ -918,7 +928,7 @@ __device__ __forceinline__ LocalAdjoint adjoint_local(const Phys &ph, double om,
 #pragma unroll
   for (int q = 0; q < Q; ++q) sE += pre[q];
   mirror_sums(pre, sx, sy, sz);
-  const Inv iv = invert(ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
+  const Inv iv = invert(ph, ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
                         ph.c * (double)sz);
   const EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
   const LamEq L = lam_eq(lam_sums(lam, k), ph, iv.W, iv.bx, iv.by, iv.bz);
@@ -1162,7 +1172,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments_adjoint(
     sE += gv[q];
   }
   mirror_sums(gv, sx, sy, sz);
-  const Inv iv = invert(ph.e_ref + sE, ph.c * sx, ph.c * sy, ph.c * sz);
+  const Inv iv = invert(ph, ph.e_ref + sE, ph.c * sx, ph.c * sy, ph.c * sz);
   const GradEM gm = chain_moments(iv, dLde[c.idx], 0.0, dLdb[c.idx], dLdb[cells + c.idx],
                                   dLdb[2 * cells + c.idx]);
   const double ax = ph.c * gm.gx, ay = ph.c * gm.gy, az = ph.c * gm.gz;

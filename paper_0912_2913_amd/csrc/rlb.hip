@@ -130,6 +130,8 @@ rlb_status validate(const rlb_params *p, long long *cells_out) {
     if (!(p->e_ref > 0.0) || !std::isfinite(p->e_ref) || !std::isfinite(p->n_ref))
       return fail(RLB_EINVAL, "deviation storage needs e_ref > 0 and finite n_ref");
   }
+  if (!(p->kappa == 0.0 || (p->kappa > 0.0 && p->kappa <= 1.0)))
+    return fail(RLB_EINVAL, "kappa (P = kappa e) must be in (0, 1], or 0 for 1/3");
   *cells_out = cells;
   return RLB_OK;
 }
@@ -500,6 +502,31 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
   ph.inv_c = 1.0 / p->c_l;
   ph.inv_c2 = 1.0 / (p->c_l * p->c_l);
   ph.k0 = 3.0 - 2.0 / (p->c_l * p->c_l);
+  ph.ad_c = ph.inv_c2;
+  ph.wfac = 4.0 / 3.0;
+  ph.kappa = 1.0 / 3.0;
+  ph.gen_eos = 0;
+  ph.eos_A = 4.0;
+  ph.eos_B = 3.0;
+  ph.eos_C = 2.0;
+  ph.eos_H = 1.0 / 3.0;
+  ph.eos_F = 1.0;
+  ph.eos_G = 1.0;
+  if (p->kappa != 0.0 && p->kappa != 1.0 / 3.0) {
+    // P = kappa e: eqs. (equil2a)/(equil2b) in the same W-form
+    const double k = p->kappa;
+    ph.kappa = k;
+    ph.gen_eos = 1;
+    ph.ad_c = 3.0 * k / (p->c_l * p->c_l);
+    ph.k0 = 3.0 - 6.0 * k / (p->c_l * p->c_l);
+    ph.wfac = 1.0 + k;
+    ph.eos_A = (1.0 + k) * (1.0 + k);
+    ph.eos_B = 4.0 * k;
+    ph.eos_C = 1.0 + k;
+    ph.eos_H = 0.5;
+    ph.eos_F = 1.0 - k;
+    ph.eos_G = 1.0 / (2.0 * k);
+  }
   const bool dev = p->storage >= ST_F32DEV;
   ph.n_ref = dev ? p->n_ref : 0.0;
   ph.e_ref = dev ? p->e_ref : 0.0;
@@ -630,6 +657,8 @@ rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *la
                             void *lam_out, double *dL_dtau, double *dL_dbeta_in,
                             double *dL_de_in) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->ph.gen_eos)
+    return fail(RLB_EINVAL, "the reverse mode is built for e = 3P (kappa = 1/3)");
   if (h->ph.eta_s > 0.0)
     return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   if (!g_state_t || !lam_next || !lam_out || lam_next == lam_out)
@@ -648,6 +677,8 @@ rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *la
 rlb_status rlb_adjoint_sweep(rlb_solver *h, const void *g_seq, int64_t seq_stride, int32_t n,
                              void *lam_a, void *lam_b, void **lam_result) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->ph.gen_eos)
+    return fail(RLB_EINVAL, "the reverse mode is built for e = 3P (kappa = 1/3)");
   if (h->ph.eta_s > 0.0)
     return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   if (n < 0 || !lam_a || !lam_b || lam_a == lam_b || !lam_result || (n > 0 && !g_seq) ||
@@ -719,6 +750,8 @@ rlb_status rlb_trajectory_g(rlb_solver *h, void *g_seq, int64_t seq_stride, int3
 rlb_status rlb_moments_adjoint(rlb_solver *h, const void *g_state_T, const double *dL_de,
                                const double *dL_dbeta, void *lam_T) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->ph.gen_eos)
+    return fail(RLB_EINVAL, "the reverse mode is built for e = 3P (kappa = 1/3)");
   if (!g_state_T || !dL_de || !dL_dbeta || !lam_T)
     return fail(RLB_EINVAL, "a required pointer is NULL");
   RLB_DISPATCH(h, launch_moments_adjoint, h, g_state_T, dL_de, dL_dbeta, lam_T);
@@ -728,6 +761,8 @@ rlb_status rlb_init_adjoint(rlb_solver *h, const double *e0, const double *beta0
                             const void *lam_0, double *dL_de0, double *dL_dbeta0,
                             double *dL_dbeta_in, double *dL_de_in) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->ph.gen_eos)
+    return fail(RLB_EINVAL, "the reverse mode is built for e = 3P (kappa = 1/3)");
   if (!e0 || !beta0 || !lam_0 || !dL_de0 || !dL_dbeta0)
     return fail(RLB_EINVAL, "a required pointer is NULL");
   RLB_DISPATCH(h, launch_init_adjoint, h, e0, beta0, lam_0, dL_de0, dL_dbeta0, dL_dbeta_in,
@@ -781,6 +816,8 @@ rlb_status rlb_hold_eta_over_s(rlb_solver *h, double eta_over_s, double d_G) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   if (!(eta_over_s >= 0.0) || !std::isfinite(eta_over_s) || !(d_G > 0.0) || !std::isfinite(d_G))
     return fail(RLB_EINVAL, "eta_over_s must be >= 0 and d_G > 0 (both finite)");
+  if (h->ph.gen_eos && eta_over_s > 0.0)
+    return fail(RLB_EINVAL, "transport quantities and the eta/s rule are defined for e = 3P (kappa = 1/3)");
   h->ph.eta_s = eta_over_s;
   h->ph.d_G = d_G;
   return RLB_OK;
@@ -789,6 +826,8 @@ rlb_status rlb_hold_eta_over_s(rlb_solver *h, double eta_over_s, double d_G) {
 rlb_status rlb_transport(rlb_solver *h, double d_G, double *T, double *s, double *eta,
                          double *eta_over_s) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->ph.gen_eos)
+    return fail(RLB_EINVAL, "transport quantities and the eta/s rule are defined for e = 3P (kappa = 1/3)");
   if (!(d_G > 0.0) || !std::isfinite(d_G)) return fail(RLB_EINVAL, "d_G must be > 0");
   if (h->ph.eta_s > 0.0 && d_G != h->ph.d_G)
     return fail(RLB_EINVAL, "d_G differs from the one eta/s is held with");

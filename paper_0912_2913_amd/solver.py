@@ -28,7 +28,7 @@ def _ptr(t: Optional[torch.Tensor]):
 
 def make_params(nx, ny, nz, batch=1, c_l=1.0, bc=((0, 0), (0, 0), (0, 0)),
                 inflow=(1.0, 1.0, 0.0, 0.0, 0.0), storage=_lib.F64, n_ref=1.0,
-                e_ref=1.0, collide=_lib.COLLIDE_AUTO) -> _lib.Params:
+                e_ref=1.0, collide=_lib.COLLIDE_AUTO, kappa=0.0) -> _lib.Params:
     p = _lib.Params()
     p.nx, p.ny, p.nz, p.batch = int(nx), int(ny), int(nz), int(batch)
     p.c_l = float(c_l)
@@ -41,6 +41,7 @@ def make_params(nx, ny, nz, batch=1, c_l=1.0, bc=((0, 0), (0, 0), (0, 0)),
     p.storage = int(storage)
     p.n_ref, p.e_ref = float(n_ref), float(e_ref)
     p.collide = int(collide)
+    p.kappa = float(kappa)
     return p
 
 
@@ -83,7 +84,8 @@ class Solver:
         s = setup
         self.setup = s
         self.params = make_params(s.nx, s.ny, s.nz, s.batch, s.c_l, s.bc, s.inflow, s.storage,
-                                  s.n_ref, s.e_ref, getattr(s, "collide", _lib.COLLIDE_AUTO))
+                                  s.n_ref, s.e_ref, getattr(s, "collide", _lib.COLLIDE_AUTO),
+                                  getattr(s, "kappa", 0.0))
         self.nx, self.ny, self.nz, self.batch = s.nx, s.ny, s.nz, s.batch
         self.cells = s.batch * s.nz * s.ny * s.nx
         self.storage = int(s.storage)

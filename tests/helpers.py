@@ -9,7 +9,7 @@ import rlb_inputs as ri
 
 def problem(s: ri.Setup) -> oracle.Problem:
     return oracle.Problem(s.nx, s.ny, s.nz, s.batch, s.c_l, s.bc, s.inflow, s.tau, s.solid,
-                          tau_cell=s.tau_cell, eta_s=s.eta_s, d_G=s.d_G)
+                          tau_cell=s.tau_cell, eta_s=s.eta_s, d_G=s.d_G, kappa=s.kappa)
 
 
 def fluid_mask(s: ri.Setup) -> np.ndarray:

@@ -134,3 +134,15 @@ def test_general_eos_reverse_sweep_matches_complex_step():
                            d_inflow=np.array([0.3, 0.1, -0.2, 0.05]))
     want = G.e0 @ v + G.tau[0] + G.e_in * 0.3 + G.beta_in @ np.array([0.1, -0.2, 0.05])
     assert want == pytest.approx(cs, rel=1e-9)
+
+
+def test_stiff_eos_needs_a_lattice_faster_than_sound():
+    """kappa = 1 gives sound speed c: at c_l = 1 it equals the lattice speed and
+    the scheme goes unphysical within 30 steps on a mildly perturbed state; at
+    c_l = 2 the same run stays physical."""
+    for c_l, ok in ((1.0, False), (2.0, True)):
+        s = ri.random_state_setup(9, 7, 8, seed=27, tau=[0.8], c_l=c_l)
+        p = problem(s)
+        p.kappa = 1.0
+        S = oracle.init(p, s.n0, s.e0, s.beta0)
+        assert (oracle.run(p, S, 30) == 0) == ok, c_l
