@@ -993,33 +993,76 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
       part[(size_t)c.L * 5 + k2] = (accum ? part[(size_t)c.L * 5 + k2] : 0.0) + out[k2];
 }
 
+// Per listed cell of the general reverse kernel, precomputed once: the 19
+// pull sources (source cell and direction, bounce-back and clamp flags) and
+// the mask of its own lambda_t entries that no update writes.  Layout [Q][n]
+// so that consecutive list entries read consecutive words.
+struct GenTable {
+  const int *src;        // [Q][n] source cell (the cell itself for bounce-back)
+  const uint8_t *srcq;   // [Q][n] source direction | 32 bounce-back | 64 clamped
+  const unsigned *info;  // [n] bit 0 solid, bit 1 inflow, bits 8.. uncovered p
+  int n;
+};
+
+__global__ __launch_bounds__(BLOCK) void k_adjoint_table(const Geom g, const Phys ph,
+                                                         const int *__restrict__ list, int n,
+                                                         int *__restrict__ src,
+                                                         uint8_t *__restrict__ srcq,
+                                                         unsigned *__restrict__ info) {
+  const int i = (int)(blockIdx.x * BLOCK + threadIdx.x);
+  if (i >= n) return;
+  const int li = list[i];
+  if (li < 0) {
+    info[i] = 0u;
+    for (int q = 0; q < Q; ++q) {
+      src[(size_t)q * n + i] = 0;
+      srcq[(size_t)q * n + i] = 0;
+    }
+    return;
+  }
+  const Cell c = cell_at(g, li);
+  const bool solid = solid_at(ph, c.idx);
+  const bool inflow = !solid && is_inflow(g, c.x, c.y, c.z);
+  unsigned m = 0u;
+  for (int p = 0; p < Q; ++p)
+    if (solid || !covered(g, ph, c, p, inflow)) m |= 1u << p;
+  info[i] = (solid ? 1u : 0u) | (inflow ? 2u : 0u) | (m << 8);
+  for (int q = 0; q < Q; ++q) {
+    const Pull p = pull_general(g, ph, c, q);
+    src[(size_t)q * n + i] = (int)p.idx;
+    srcq[(size_t)q * n + i] = (uint8_t)(p.q | (p.bounce ? 32 : 0) | (p.clamped ? 64 : 0));
+  }
+}
+
 // General part of the reverse step, over the listed cells (list[i] = linear
 // cell index, -1 = padding; each instance's cells fill whole workgroups).
 // Zeroes the entries of lambda_t that no update writes, routes inflow cells'
 // lambda_{t+1} into the inflow gradient, and scatters through the general
-// pull (bounce-back to the cell's own opposite entry; clamped pulls into
-// `scratch`, indexed by the reading cell, for k_adjoint_faces).
+// pull read from T (bounce-back to the cell's own opposite entry; clamped
+// pulls into `scratch`, indexed by the reading cell, for k_adjoint_faces).
 // part[blk][5] = (dtau, de_in, dbeta_in[3]) partials of this workgroup
 // (accumulated across steps like k_adjoint's).
 template <int ST, class TC>
 __global__ __launch_bounds__(BLOCK) void k_adjoint_general(
-    const Geom g, const Phys ph, const int *__restrict__ list,
+    const Geom g, const Phys ph, const int *__restrict__ list, const GenTable T,
     const typename Codec<ST, TC>::elem *__restrict__ S, const LamT *__restrict__ lam_next,
     LamT *__restrict__ lam_out, LamT *__restrict__ scratch, double *__restrict__ part,
     const InflowState in, int accum) {
   using Cd = Codec<ST, TC>;
-  const int li = list[(size_t)blockIdx.x * BLOCK + threadIdx.x];
+  const int i = (int)(blockIdx.x * BLOCK + threadIdx.x);
+  const int li = list[i];
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (li >= 0) {
-    const Cell c = cell_at(g, li);
-    const bool solid = solid_at(ph, c.idx);
-    const bool inflow = !solid && is_inflow(g, c.x, c.y, c.z);
+    const unsigned inf = T.info[i];
+    const bool solid = inf & 1u;
+    const bool inflow = inf & 2u;
+    const unsigned unc = inf >> 8;
     for (int p = 0; p < Q; ++p)
-      if (solid || !covered(g, ph, c, p, inflow)) lam_out[at(p, c.idx)] = 0.0;
+      if ((unc >> p) & 1u) lam_out[at(p, li)] = 0.0;
     if (inflow) {
       double lam[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, c.idx)];
+      for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, li)];
       const double g2 = 1.0 / (1.0 - (in.bx * in.bx + in.by * in.by + in.bz * in.bz));
       const double W = (4.0 / 3.0) * in.e * g2;
       const EqCoef<double> k = eq_coef<double>(ph, 0.0, in.e, W, in.bx, in.by, in.bz);
@@ -1030,26 +1073,25 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_general(
     } else if (!solid) {
       double pre[Q], lam[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const Pull p = pull_general(g, ph, c, q);
-        pre[q] = (double)Cd::dec(S[at(p.q, p.idx)]);
-      }
+      for (int q = 0; q < Q; ++q)
+        pre[q] = (double)Cd::dec(S[at(T.srcq[(size_t)q * T.n + i] & 31, T.src[(size_t)q * T.n + i])]);
 #pragma unroll
-      for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, c.idx)];
-      const LocalAdjoint a = adjoint_local(ph, omega_of(ph, c.b, c.idx), pre, lam);
+      for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, li)];
+      const int b = li / g.per;
+      const LocalAdjoint a = adjoint_local(ph, omega_of(ph, b, li), pre, lam);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const double mu = adjoint_mu(a, lam[q], q);
-        const Pull p = pull_general(g, ph, c, q);
-        if (p.bounce)
-          lam_out[at(OPP[q], c.idx)] = mu;
-        else if (p.clamped)
-          scratch[at(q, c.idx)] = mu;
+        const unsigned fl = T.srcq[(size_t)q * T.n + i];
+        if (fl & 32u)
+          lam_out[at(OPP[q], li)] = mu;
+        else if (fl & 64u)
+          scratch[at(q, li)] = mu;
         else
-          lam_out[at(q, p.idx)] = mu;
+          lam_out[at(q, T.src[(size_t)q * T.n + i])] = mu;
       }
       acc[0] = a.dtau;
-      if (ph.dtau_cell) ph.dtau_cell[c.idx] += a.dtau;
+      if (ph.dtau_cell) ph.dtau_cell[li] += a.dtau;
     }
   }
   double out[5];
@@ -1076,12 +1118,14 @@ struct Faces {
   long long start[7];
 };
 
-// Adds the contributions of clamped pulls (readers on an outflow face whose
-// source was clamped onto the same face) to lambda_t, in a fixed order.
-template <class Lm>
-__global__ __launch_bounds__(BLOCK) void k_adjoint_faces(const Geom g, const Phys ph, const Faces F,
-                                                         const Lm *__restrict__ scratch,
-                                                         Lm *__restrict__ lam_out) {
+// Readers whose clamped pulls land on face cells, precomputed once: for
+// face cell t (flattened over the faces) and direction p = 1..18, tgt[t][p-1]
+// = the target cell (-1 when the cell is solid or listed by an earlier face)
+// and rd[t][p-1][m-1], m = 1..7, the reading cell of clamp pattern m (bit k
+// set: clamped along axis k), or -1.  A cell on several faces belongs to the
+// first face that lists it.
+__global__ __launch_bounds__(BLOCK) void k_faces_table(const Geom g, const Phys ph, const Faces F,
+                                                       int *__restrict__ tgt, int *__restrict__ rd) {
   const long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
   if (t >= F.start[F.count]) return;
   int f = 0;
@@ -1095,58 +1139,84 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_faces(const Geom g, const Phy
   co[v] = (int)(r % g.n[v]);
   const int b = (int)(r / g.n[v]);
   co[a] = F.side[f] == 0 ? 0 : g.n[a] - 1;
-  // a cell on several faces is handled by the first face listing it
+  bool skip = false;
   for (int f2 = 0; f2 < f; ++f2) {
     const int a2 = F.axis[f2];
-    if (co[a2] == (F.side[f2] == 0 ? 0 : g.n[a2] - 1)) return;
+    if (co[a2] == (F.side[f2] == 0 ? 0 : g.n[a2] - 1)) skip = true;
   }
   const long long yi = cell_index(g, b, co[0], co[1], co[2]);
-  if (solid_at(ph, yi)) return;
+  skip = skip || solid_at(ph, yi);
   for (int p = 1; p < Q; ++p) {
+    const size_t k = (size_t)t * (Q - 1) + (p - 1);
+    tgt[k] = skip ? -1 : (int)yi;
     const int e[3] = {EX[p], EY[p], EZ[p]};
     int nrm[3];
     bool hn[3], hc[3];
-    for (int k = 0; k < 3; ++k) {
-      const int n = g.n[k];
-      if (e[k] == 0) {
-        nrm[k] = co[k];
-        hn[k] = true;
-        hc[k] = false;
+    for (int d = 0; d < 3; ++d) {
+      const int n = g.n[d];
+      if (e[d] == 0) {
+        nrm[d] = co[d];
+        hn[d] = true;
+        hc[d] = false;
         continue;
       }
-      int rr = co[k] + e[k];
-      if (g.periodic[k]) {
+      int rr = co[d] + e[d];
+      if (g.periodic[d]) {
         if (rr < 0) rr += n;
         if (rr >= n) rr -= n;
-        hn[k] = true;
+        hn[d] = true;
       } else {
-        hn[k] = rr >= 0 && rr < n;
+        hn[d] = rr >= 0 && rr < n;
       }
-      nrm[k] = rr;
-      hc[k] = !g.periodic[k] && ((e[k] == 1 && co[k] == 0) || (e[k] == -1 && co[k] == n - 1));
+      nrm[d] = rr;
+      hc[d] = !g.periodic[d] && ((e[d] == 1 && co[d] == 0) || (e[d] == -1 && co[d] == n - 1));
     }
-    Lm acc = (Lm)0;
-    bool any = false;
     for (int m = 1; m < 8; ++m) {
       int rc[3];
-      bool ok = true;
-      for (int k = 0; k < 3; ++k) {
-        if ((m >> k) & 1) {
-          ok = ok && hc[k];
-          rc[k] = co[k];
+      bool ok = !skip;
+      for (int d = 0; d < 3; ++d) {
+        if ((m >> d) & 1) {
+          ok = ok && hc[d];
+          rc[d] = co[d];
         } else {
-          ok = ok && hn[k];
-          rc[k] = nrm[k];
+          ok = ok && hn[d];
+          rc[d] = nrm[d];
         }
       }
-      if (!ok) continue;
-      const long long ri = cell_index(g, b, rc[0], rc[1], rc[2]);
-      if (solid_at(ph, ri) || is_inflow(g, rc[0], rc[1], rc[2])) continue;
+      int reader = -1;
+      if (ok) {
+        const long long ri = cell_index(g, b, rc[0], rc[1], rc[2]);
+        if (!solid_at(ph, ri) && !is_inflow(g, rc[0], rc[1], rc[2])) reader = (int)ri;
+      }
+      rd[k * 7 + (m - 1)] = reader;
+    }
+  }
+}
+
+// Adds the contributions of clamped pulls (readers on an outflow face whose
+// source was clamped onto the same face) to lambda_t, in a fixed order, from
+// the precomputed reader table: one thread per (face cell, direction).
+template <class Lm>
+__global__ __launch_bounds__(BLOCK) void k_adjoint_faces(long long npairs,
+                                                         const int *__restrict__ tgt,
+                                                         const int *__restrict__ rd,
+                                                         const Lm *__restrict__ scratch,
+                                                         Lm *__restrict__ lam_out) {
+  const long long k = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= npairs) return;
+  const int yi = tgt[k];
+  if (yi < 0) return;
+  const int p = (int)(k % (Q - 1)) + 1;
+  Lm acc = (Lm)0;
+  bool any = false;
+  for (int m = 0; m < 7; ++m) {
+    const int ri = rd[k * 7 + m];
+    if (ri >= 0) {
       acc += scratch[at(p, ri)];
       any = true;
     }
-    if (any) lam_out[at(p, yi)] += acc;
   }
+  if (any) lam_out[at(p, yi)] += acc;
 }
 
 // lambda_T = (d(e, beta)/d S_T)^T (dL/de, dL/dbeta), cell-local.

@@ -38,7 +38,12 @@ struct rlb_solver {
   int *d_glist;
   int *d_gstart;  // [batch + 1] first workgroup of each instance in the list
   double *d_part2;
+  int *d_gsrc;          // general-cell pull table (see GenTable)
+  uint8_t *d_gsrcq;
+  unsigned *d_ginfo;
+  int *d_ftgt, *d_frd;  // face-reader table (see k_faces_table)
   int n_gblk;
+  int glist_total;  // list length including padding
   bool glist_ready;
   bool rev_pending;  // reverse-step partials accumulated and not yet reduced
   bool held;         // solid cells or an inflow plane exist (held cells)
@@ -330,7 +335,24 @@ rlb_status build_adjoint_list(rlb_solver *h) {
     RLB_HIP(hipMemcpy(h->d_glist, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice));
     RLB_HIP(hipMemcpy(h->d_gstart, start.data(), start.size() * sizeof(int),
                       hipMemcpyHostToDevice));
+    const size_t n = list.size();
+    RLB_HIP(hipMalloc(&h->d_gsrc, (size_t)Q * n * sizeof(int)));
+    RLB_HIP(hipMalloc(&h->d_gsrcq, (size_t)Q * n));
+    RLB_HIP(hipMalloc(&h->d_ginfo, n * sizeof(unsigned)));
+    hipLaunchKernelGGL(k_adjoint_table, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                       h->stream, h->g, h->ph, (const int *)h->d_glist, (int)n, h->d_gsrc,
+                       h->d_gsrcq, h->d_ginfo);
+    RLB_HIP(hipGetLastError());
   }
+  if (h->faces.count > 0) {
+    const long long nf = h->faces.start[h->faces.count];
+    RLB_HIP(hipMalloc(&h->d_ftgt, (size_t)nf * (Q - 1) * sizeof(int)));
+    RLB_HIP(hipMalloc(&h->d_frd, (size_t)nf * (Q - 1) * 7 * sizeof(int)));
+    hipLaunchKernelGGL(k_faces_table, dim3((unsigned)((nf + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                       h->stream, h->g, h->ph, h->faces, h->d_ftgt, h->d_frd);
+    RLB_HIP(hipGetLastError());
+  }
+  h->glist_total = (int)list.size();
   h->glist_ready = true;
   return RLB_OK;
 }
@@ -343,16 +365,18 @@ rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_next, vo
   hipLaunchKernelGGL((k_adjoint<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
                      h->ph, (const El *)S, (const LamT *)lam_next, (LamT *)lam_out, h->d_part_rev,
                      accum);
-  if (h->n_gblk > 0)
+  if (h->n_gblk > 0) {
+    const GenTable T{h->d_gsrc, h->d_gsrcq, h->d_ginfo, h->glist_total};
     hipLaunchKernelGGL((k_adjoint_general<ST, TC>), dim3(h->n_gblk), dim3(BLOCK), 0, h->stream,
-                       h->g, h->ph, (const int *)h->d_glist, (const El *)S,
+                       h->g, h->ph, (const int *)h->d_glist, T, (const El *)S,
                        (const LamT *)lam_next, (LamT *)lam_out, (LamT *)h->d_scratch, h->d_part2,
                        h->in, accum);
+  }
   if (h->faces.count > 0) {
-    const long long nf = h->faces.start[h->faces.count];
-    hipLaunchKernelGGL(k_adjoint_faces<LamT>, dim3((unsigned)((nf + BLOCK - 1) / BLOCK)),
-                       dim3(BLOCK), 0, h->stream, h->g, h->ph, h->faces,
-                       (const LamT *)h->d_scratch, (LamT *)lam_out);
+    const long long npairs = h->faces.start[h->faces.count] * (Q - 1);
+    hipLaunchKernelGGL(k_adjoint_faces<LamT>, dim3((unsigned)((npairs + BLOCK - 1) / BLOCK)),
+                       dim3(BLOCK), 0, h->stream, npairs, (const int *)h->d_ftgt,
+                       (const int *)h->d_frd, (const LamT *)h->d_scratch, (LamT *)lam_out);
   }
   h->rev_pending = true;
   RLB_HIP(hipGetLastError());
@@ -443,6 +467,11 @@ void free_solver(rlb_solver *h) {
   if (h->d_glist) (void)hipFree(h->d_glist);
   if (h->d_gstart) (void)hipFree(h->d_gstart);
   if (h->d_part2) (void)hipFree(h->d_part2);
+  if (h->d_gsrc) (void)hipFree(h->d_gsrc);
+  if (h->d_gsrcq) (void)hipFree(h->d_gsrcq);
+  if (h->d_ginfo) (void)hipFree(h->d_ginfo);
+  if (h->d_ftgt) (void)hipFree(h->d_ftgt);
+  if (h->d_frd) (void)hipFree(h->d_frd);
   if (h->d_omega_cell) (void)hipFree(h->d_omega_cell);
   if (h->d_dtau_cell) (void)hipFree(h->d_dtau_cell);
   if (h->d_bad) (void)hipFree(h->d_bad);
