@@ -786,12 +786,16 @@ struct LamSums {
   T Slw, SW, Vx, Vy, Vz, lw0;
 };
 
+// With pre != null also dt = sum_q lam_q (pre_q - g^eq_q) (same order as a
+// separate loop), so that pre is dead after this single pass.
 template <class T>
-__device__ __forceinline__ LamSums<T> lam_sums(const T (&lam)[Q], const EqCoef<T> &k) {
+__device__ __forceinline__ LamSums<T> lam_sums(const T (&lam)[Q], const EqCoef<T> &k,
+                                               const T *pre = nullptr, T *dt = nullptr) {
   LamSums<T> r;
   r.Slw = r.SW = (T)0;
   T u[Q];
   u[0] = (T)0;
+  T d = (T)0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const T lw = lam[q] * (T)WQ[q];
@@ -804,8 +808,10 @@ __device__ __forceinline__ LamSums<T> lam_sums(const T (&lam)[Q], const EqCoef<T
       r.SW += lw * (b * ((T)3 + (T)4.5 * b) - k.s);
       u[q] = lw * ((T)3 + (T)9 * b);
     }
+    if (pre) d += lam[q] * (pre[q] - geq_dev(k, q));
   }
   mirror_sums(u, r.Vx, r.Vy, r.Vz);
+  if (dt) *dt = d;
   return r;
 }
 
@@ -931,7 +937,8 @@ __device__ __forceinline__ LocalAdjoint adjoint_local(const Phys &ph, double om,
   const Inv iv = invert(ph, ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
                         ph.c * (double)sz);
   const EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
-  const LamEq L = lam_eq(lam_sums(lam, k), ph, iv.W, iv.bx, iv.by, iv.bz);
+  T dt;
+  const LamEq L = lam_eq(lam_sums(lam, k, pre, &dt), ph, iv.W, iv.bx, iv.by, iv.bz);
   const GradEM gm = chain_moments(iv, L.Le, L.LW, L.Lbx, L.Lby, L.Lbz);
   LocalAdjoint r;
   r.om1 = 1.0 - om;
@@ -939,9 +946,6 @@ __device__ __forceinline__ LocalAdjoint adjoint_local(const Phys &ph, double om,
   r.ax = om * ph.c * gm.gx;
   r.ay = om * ph.c * gm.gy;
   r.az = om * ph.c * gm.gz;
-  T dt = (T)0;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) dt += lam[q] * (pre[q] - geq_dev(k, q));
   r.dtau = om * om * (double)dt;
   return r;
 }
