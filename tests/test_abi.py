@@ -79,6 +79,9 @@ def test_buffer_layout_pads_direction_stride(L):
     dict(storage=9),
     dict(storage=4, e_ref=0.0),
     dict(nx=2048, ny=2048, nz=1024),             # > 2^31 cells
+    dict(kappa=1.5),                             # P = kappa e beyond the causal limit
+    dict(kappa=-0.2),
+    dict(collide=5),
 ])
 def test_invalid_problem_statement_is_rejected(L, bad):
     from paper_0912_2913_amd.solver import make_params
