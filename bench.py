@@ -217,6 +217,35 @@ def bench_adjoint(s, T, warmup, reps=4):
             "adjoint_kernel_ratio": t_sw / fwd}
 
 
+def bench_tubes(T=2000):
+    """64 shock tubes of 2048 cells in one lattice (FP32): launch-bound, so the
+    figures are microseconds per step and the wall time of a T-step gradient
+    with sqrt(T) checkpointing (forward + reverse through the scheduler)."""
+    import torch
+
+    import rlb_inputs as ri
+    from paper_0912_2913_amd.autograd import rlb_run
+    from paper_0912_2913_amd.solver import Solver
+
+    s = ri.tube_batch(storage=ri.F32)[0]
+    sv = Solver(s)
+    sv.step(10)
+    fwd = time_steps(sv.step, T, sv.stream) / T
+    sv.close()
+    out = {"forward_us_per_step": round(1e6 * fwd, 2)}
+    for rep in range(2):  # the second repetition is timed (the first builds the tables)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tau = torch.tensor(s.tau, device="cuda", requires_grad=True)
+        e, _ = rlb_run(s, T, tau=tau)
+        e.sum().backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    out["gradient_ms"] = round(1e3 * dt, 1)
+    out["gradient_us_per_step"] = round(1e6 * dt / T, 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,6 +342,17 @@ def main():
         for st in (ri.F64, ri.F32):
             out["adjoint_sphere_" + ri.STORAGE_NAMES[st]] = {
                 k: round(v, 4) for k, v in bench_adjoint(ri.sphere(storage=st), 60, 5).items()}
+        out["tube_batch_64x2048_f32"] = bench_tubes()
+        # in-place (AA-pattern) streaming: one state buffer instead of two
+        sp = ri.sphere()
+        sp.inplace = True
+        dta, _ = bench_forward(sp, 200, 20)
+        dt2, _ = bench_forward(ri.sphere(), 200, 20)
+        out["inplace_sphere_f64"] = {
+            "ms_per_step": round(1e3 * dta / 200, 5), "mlups": round(s.cells * 200 / dta / 1e6, 1),
+            "two_buffer_ms_per_step": round(1e3 * dt2 / 200, 5),
+            "speed_vs_two_buffer": round(dt2 / dta, 3),
+            "state_bytes": int(2 * Q * s.cells * 8), "two_buffer_state_bytes": int(4 * Q * s.cells * 8)}
         out["copy_probe_GBs"] = round(copy_probe(), 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s)

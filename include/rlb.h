@@ -37,6 +37,15 @@
  *    clamped into the domain); INFLOW holds the face plane at the equilibrium
  *    of (inflow_n, inflow_e, inflow_beta).  Solid cells reflect by half-way
  *    bounce-back and are never updated.
+ *  - In-place streaming (rlb_params.inplace = 1): the solver keeps one state
+ *    buffer (pop_a; pop_b may be NULL) and alternates two kernels.  After an
+ *    even number of steps pop_a holds S_t with S_t(x)_q at slot opp(q) of x
+ *    (the "swapped" layout: element (pop, opp(q), x) in the formula above);
+ *    after an odd number it holds the pulled, pre-collision values of the
+ *    next step, P(x)_q at slot q, from which S_t is not recoverable
+ *    everywhere.  rlb_moments and rlb_transport then need an even step count;
+ *    the g-only, reverse-mode and held-eta/s entry points are not available.
+ *    Same HBM traffic per step, half the state memory.
  *  - Adjoint buffers ("lambda"): one block in the same brick layout, double
  *    for every storage.
  *  - Device pointers address memory on the solver's device; every call that
@@ -94,6 +103,7 @@ typedef struct {
   int32_t collide;           /* rlb_collide                                      */
   double kappa;              /* equation of state P = kappa e, 0 < kappa <= 1;   */
                              /* 0 selects 1/3 (e = 3P, the paper's simulations)  */
+  int32_t inplace;           /* 1: one state buffer, in-place streaming (below)  */
 } rlb_params;
 
 /* Layout of one population buffer for these parameters: q_stride (cells
@@ -110,7 +120,8 @@ rlb_status rlb_buffer_layout(const rlb_params *p, int64_t *q_stride, int64_t *st
  *          g^eq(e0, beta0)) on fluid cells, the inflow equilibrium on inflow
  *          cells, zeros on solid cells (in both pop_a and pop_b).
  *  pop_a, pop_b: caller-owned device buffers of state_bytes each, aliased by
- *          the solver until rlb_destroy; the steps ping-pong between them.
+ *          the solver until rlb_destroy; the steps ping-pong between them
+ *          (in-place streaming: pop_a only, pop_b unused and may be NULL).
  *  stream: hipStream_t (NULL = default stream) for all of the solver's work.
  * Validation: extents >= 1 (>= 2 on non-periodic axes); periodic on both or
  * neither face of an axis; at most one INFLOW face; inflow_e > 0 and
@@ -156,7 +167,8 @@ rlb_status rlb_current(rlb_solver *h, void **state);
  * any may be NULL; zeros on solid cells).  sums: host double [batch][5] =
  * (sum f, sum g, sum g c_x, sum g c_y, sum g c_z) over non-solid cells,
  * reduced in a fixed order in FP64 (bitwise reproducible), or NULL.  With
- * sums != NULL the call synchronises the stream. */
+ * sums != NULL the call synchronises the stream.  In-place streaming:
+ * RLB_EINVAL after an odd number of steps (S_t is not stored then). */
 rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double *sums);
 
 /* Fields e [cells] and beta [3][cells] (device double, either may be NULL)

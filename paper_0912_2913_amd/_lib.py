@@ -39,6 +39,7 @@ class Params(ctypes.Structure):
         ("n_ref", ctypes.c_double), ("e_ref", ctypes.c_double),
         ("collide", ctypes.c_int32),
         ("kappa", ctypes.c_double),
+        ("inplace", ctypes.c_int32),
     ]
 
 

@@ -613,7 +613,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const Geom g, const Phys ph,
                                                    const typename Codec<ST, TC>::elem *__restrict__ Sg,
                                                    double *__restrict__ n, double *__restrict__ e,
                                                    double *__restrict__ beta,
-                                                   double *__restrict__ part) {
+                                                   double *__restrict__ part, int swap) {
   using Cd = Codec<ST, TC>;
   const Cell c = decode_cell(g);
   const size_t cells = (size_t)g.batch * g.per;
@@ -627,8 +627,9 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const Geom g, const Phys ph,
       double N = 0.0, Eg = 0.0, sx, sy, sz, gv[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        if (Sf) N += (double)Cd::dec(Sf[at(q, c.idx)]);
-        gv[q] = (double)Cd::dec(Sg[at(q, c.idx)]);
+        const int sq = swap ? OPP[q] : q;  // in-place layout: S_q at slot opp(q)
+        if (Sf) N += (double)Cd::dec(Sf[at(sq, c.idx)]);
+        gv[q] = (double)Cd::dec(Sg[at(sq, c.idx)]);
         Eg += gv[q];
       }
       mirror_sums(gv, sx, sy, sz);
@@ -666,7 +667,8 @@ __global__ __launch_bounds__(BLOCK) void k_transport(const Geom g, const Phys ph
                                                      const typename Codec<ST, TC>::elem *__restrict__ Sf,
                                                      const typename Codec<ST, TC>::elem *__restrict__ Sg,
                                                      double *__restrict__ temp, double *__restrict__ ent,
-                                                     double *__restrict__ eta, double *__restrict__ eos) {
+                                                     double *__restrict__ eta, double *__restrict__ eos,
+                                                     int swap) {
   using Cd = Codec<ST, TC>;
   const Cell c = decode_cell(g);
   if (!c.active) return;
@@ -675,8 +677,9 @@ __global__ __launch_bounds__(BLOCK) void k_transport(const Geom g, const Phys ph
     double N = ph.n_ref, Eg = ph.e_ref, sx, sy, sz, gv[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      N += (double)Cd::dec(Sf[at(q, c.idx)]);
-      gv[q] = (double)Cd::dec(Sg[at(q, c.idx)]);
+      const int sq = swap ? OPP[q] : q;
+      N += (double)Cd::dec(Sf[at(sq, c.idx)]);
+      gv[q] = (double)Cd::dec(Sg[at(sq, c.idx)]);
       Eg += gv[q];
     }
     mirror_sums(gv, sx, sy, sz);
@@ -1315,6 +1318,292 @@ __global__ __launch_bounds__(BLOCK) void k_classify(const Geom g, const uint8_t 
     if (solid[cell_index(g, c.b, sx, sy, sz)]) v |= CLS_NEAR;
   }
   cls[c.idx] = v;
+}
+
+// ---------------------------------------------------------------------------
+// In-place streaming (AA pattern): one state buffer A, two alternating
+// kernels.  Representation "swapped": A holds S_t(x)_q at slot opp(q) of x
+// itself; representation "streamed": A holds the pulled, pre-collision
+// value P(x)_q = S(source_q(x)) at slot q of x.
+//   k_aa_local  (streamed -> swapped): collide in place at the own cell.
+//   k_aa_pull   (swapped -> streamed): pull, collide, and push every
+//     post-collision S(x)_q to each cell that will pull it: the plain
+//     neighbour x + e_q, x itself (slot opp(q)) when x's pull of opp(q)
+//     bounces off a solid, and the readers whose pull of q is clamped onto
+//     x (from the face-reader table).  Each location of A is read and
+//     written by the same cell only, so the kernel is race-free in place.
+// A value needed by two readers, a face cell's S(x)_q pulled both by its
+// plain neighbour and by a face reader whose pull is clamped onto x, is
+// copied by k_aa_local into the face buffer Fb ([2][Q][face cells], one copy
+// per non-periodic face the cell lies on); clamped pulls read it there.
+struct FaceMap {
+  int id[3][2];          // face index of (axis, side), -1 on a periodic axis
+  long long start[7];    // first flattened position of each face
+  long long nf;          // face cells in total
+  int count;
+};
+
+__device__ __forceinline__ long long face_pos(const Geom &g, const FaceMap &fm, int f, int a,
+                                              int b, int x, int y, int z) {
+  const int co[3] = {x, y, z};
+  const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
+  return fm.start[f] + ((long long)b * g.n[v] + co[v]) * g.n[u] + co[u];
+}
+
+// Relax both populations of one update in place (pre -> post) with the same
+// arithmetic as k_step; returns whether the update was unphysical.
+template <class Cd>
+__device__ __forceinline__ bool collide_inplace(const Geom &g, const Phys &ph, const Cell &c,
+                                                typename Cd::calc (&pg)[Q],
+                                                typename Cd::calc (&pf)[Q]) {
+  using T = typename Cd::calc;
+  T sE = (T)0, sx, sy, sz;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) sE += pg[q];
+  mirror_sums(pg, sx, sy, sz);
+  const Inv iv = invert(ph, ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
+                        ph.c * (double)sz);
+  EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
+  const T om = (T)omega_of(ph, c.b, c.idx);
+  T sN = (T)0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) sN += pf[q];
+  const double N = ph.n_ref + (double)sN;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) pg[q] = pg[q] + om * (geq_dev(k, q) - pg[q]);
+  k.N = (T)N;
+  k.Nd = (T)(N - ph.n_ref);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) pf[q] = pf[q] + om * (feq_dev(k, q) - pf[q]);
+  return iv.bad;
+}
+
+// Initial state into the in-place layout: a state written in the natural
+// layout is permuted (slot q -> slot opp(q)) cell by cell, and face cells
+// fill their copies in Fb.
+template <int ST, class TC>
+__global__ __launch_bounds__(BLOCK) void k_aa_swap(const Geom g, const Phys ph, const FaceMap fm,
+                                                   typename Codec<ST, TC>::elem *__restrict__ A,
+                                                   typename Codec<ST, TC>::elem *__restrict__ Fb) {
+  using El = typename Codec<ST, TC>::elem;
+  const Cell c = decode_cell(g);
+  if (!c.active || solid_at(ph, c.idx)) return;
+  const size_t qs = (size_t)g.qs;
+  El v[2 * Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    v[q] = A[at(q, c.idx)];
+    v[Q + q] = A[Q * qs + at(q, c.idx)];
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    A[at(OPP[q], c.idx)] = v[q];
+    A[Q * qs + at(OPP[q], c.idx)] = v[Q + q];
+  }
+  const int co[3] = {c.x, c.y, c.z};
+  for (int a = 0; a < 3; ++a) {
+    if (g.periodic[a]) continue;
+    const int sd = co[a] == 0 ? 0 : (co[a] == g.n[a] - 1 ? 1 : -1);
+    if (sd < 0) continue;
+    const long long t = face_pos(g, fm, fm.id[a][sd], a, c.b, c.x, c.y, c.z);
+    for (int q = 0; q < 2 * Q; ++q) Fb[(size_t)q * fm.nf + t] = v[q];
+  }
+}
+
+template <int ST, class TC>
+__global__ __launch_bounds__(BLOCK) void k_aa_local(const Geom g, const Phys ph, const FaceMap fm,
+                                                    typename Codec<ST, TC>::elem *__restrict__ A,
+                                                    typename Codec<ST, TC>::elem *__restrict__ Fb,
+                                                    const HeldEq<typename Codec<ST, TC>::elem> in_eq,
+                                                    unsigned long long *__restrict__ counters) {
+  using Cd = Codec<ST, TC>;
+  using T = typename Cd::calc;
+  using El = typename Cd::elem;
+  const Cell c = decode_cell(g);
+  bool bad = false;
+  if (c.active && !solid_at(ph, c.idx)) {
+    const size_t qs = (size_t)g.qs;
+    El *__restrict__ Af = A;
+    El *__restrict__ Ag = A + Q * qs;
+    const bool inflow = is_inflow(g, c.x, c.y, c.z);
+    El of[Q], og[Q];
+    if (inflow) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        of[q] = in_eq.v[q];
+        og[q] = in_eq.v[Q + q];
+      }
+    } else {
+      T pf[Q], pg[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        pf[q] = Cd::dec(Af[at(q, c.idx)]);
+        pg[q] = Cd::dec(Ag[at(q, c.idx)]);
+      }
+      bad = collide_inplace<Cd>(g, ph, c, pg, pf);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        of[q] = Cd::enc(pf[q]);
+        og[q] = Cd::enc(pg[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      Af[at(OPP[q], c.idx)] = of[q];
+      Ag[at(OPP[q], c.idx)] = og[q];
+    }
+    const int co[3] = {c.x, c.y, c.z};
+    for (int a = 0; a < 3; ++a) {
+      if (g.periodic[a]) continue;
+      const int side = co[a] == 0 ? 0 : (co[a] == g.n[a] - 1 ? 1 : -1);
+      for (int sd = 0; sd < 2; ++sd) {
+        if (side != sd) continue;
+        const long long t = face_pos(g, fm, fm.id[a][sd], a, c.b, c.x, c.y, c.z);
+        for (int q = 0; q < Q; ++q) {
+          Fb[(size_t)q * fm.nf + t] = of[q];
+          Fb[(size_t)(Q + q) * fm.nf + t] = og[q];
+        }
+      }
+    }
+  }
+  count_lanes(bad, counters, 0);
+}
+
+template <int ST, class TC>
+__global__ __launch_bounds__(BLOCK) void k_aa_pull(const Geom g, const Phys ph, const FaceMap fm,
+                                                   typename Codec<ST, TC>::elem *__restrict__ A,
+                                                   const typename Codec<ST, TC>::elem *__restrict__ Fb,
+                                                   const int *__restrict__ ftgt,
+                                                   const int *__restrict__ frd,
+                                                   const HeldEq<typename Codec<ST, TC>::elem> in_eq,
+                                                   unsigned long long *__restrict__ counters) {
+  using Cd = Codec<ST, TC>;
+  using T = typename Cd::calc;
+  using El = typename Cd::elem;
+  const Cell c = decode_cell(g);
+  bool bad = false;
+  if (c.active && !solid_at(ph, c.idx)) {
+    const size_t qs = (size_t)g.qs;
+    El *__restrict__ Af = A;
+    El *__restrict__ Ag = A + Q * qs;
+    const bool inflow = is_inflow(g, c.x, c.y, c.z);
+    const bool plain = adjoint_plain(g, ph, c);
+    const FaceCorr fc = face_corr(g, c);
+    El of[Q], og[Q];
+    if (inflow) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        of[q] = in_eq.v[q];
+        og[q] = in_eq.v[Q + q];
+      }
+    } else {
+      T pf[Q], pg[Q];
+      if (plain) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const size_t o = at(OPP[q], src_fast(g, c, fc, q));
+          pf[q] = Cd::dec(Af[o]);
+          pg[q] = Cd::dec(Ag[o]);
+        }
+      } else {
+        for (int q = 0; q < Q; ++q) {
+          const Pull p = pull_general(g, ph, c, q);
+          // the first clamped axis names the face copy to read
+          const int co[3] = {c.x, c.y, c.z};
+          const int e[3] = {EX[q], EY[q], EZ[q]};
+          int a = -1, sd = 0;
+          for (int k = 2; k >= 0; --k) {
+            if (g.periodic[k]) continue;
+            const int r = co[k] - e[k];
+            if (r < 0 || r >= g.n[k]) {
+              a = k;
+              sd = r < 0 ? 0 : 1;
+            }
+          }
+          if (p.clamped && !p.bounce && a >= 0) {  // bounce-back takes precedence
+            const long long src = p.idx;
+            const long long rem = src - (long long)c.b * g.per;
+            const int sx = (int)(rem % g.n[0]);
+            const int sy = (int)((rem / g.n[0]) % g.n[1]);
+            const int sz = (int)(rem / ((long long)g.n[0] * g.n[1]));
+            const long long t = face_pos(g, fm, fm.id[a][sd], a, c.b, sx, sy, sz);
+            pf[q] = Cd::dec(Fb[(size_t)q * fm.nf + t]);
+            pg[q] = Cd::dec(Fb[(size_t)(Q + q) * fm.nf + t]);
+          } else {
+            // plain source: S(src)_q sits at slot opp(q); bounce-back
+            // (p.idx = c.idx, p.q = opp(q)): S(x)_opp(q) sits at slot q
+            const size_t o = at(OPP[p.q], p.idx);
+            pf[q] = Cd::dec(Af[o]);
+            pg[q] = Cd::dec(Ag[o]);
+          }
+        }
+      }
+      bad = collide_inplace<Cd>(g, ph, c, pg, pf);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        of[q] = Cd::enc(pf[q]);
+        og[q] = Cd::enc(pg[q]);
+      }
+    }
+    if (plain) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const size_t o = at(q, src_fast(g, c, fc, OPP[q]));  // x + e_q
+        Af[o] = of[q];
+        Ag[o] = og[q];
+      }
+    } else {
+      const int co[3] = {c.x, c.y, c.z};
+      // this cell's entry in the face-reader table (first face listing it)
+      long long ft = -1;
+      for (int f = 0; f < fm.count && ft < 0; ++f) {
+        for (int a = 0; a < 3; ++a)
+          for (int sd = 0; sd < 2; ++sd)
+            if (fm.id[a][sd] == f && co[a] == (sd == 0 ? 0 : g.n[a] - 1))
+              ft = face_pos(g, fm, f, a, c.b, c.x, c.y, c.z);
+      }
+      for (int q = 0; q < Q; ++q) {
+        // plain receiver x + e_q
+        int r[3];
+        bool in = true;
+        for (int a = 0; a < 3; ++a) {
+          const int e = a == 0 ? EX[q] : (a == 1 ? EY[q] : EZ[q]);
+          r[a] = co[a] + e;
+          if (g.periodic[a]) {
+            if (r[a] < 0) r[a] += g.n[a];
+            if (r[a] >= g.n[a]) r[a] -= g.n[a];
+          } else if (r[a] < 0 || r[a] >= g.n[a]) {
+            in = false;
+          }
+        }
+        if (in) {
+          const long long ri = cell_index(g, c.b, r[0], r[1], r[2]);
+          if (!solid_at(ph, ri) && !is_inflow(g, r[0], r[1], r[2])) {
+            Af[at(q, ri)] = of[q];
+            Ag[at(q, ri)] = og[q];
+          }
+        }
+        // bounce-back receiver: this cell, when its pull of opp(q) hits a solid
+        if (!inflow && pull_general(g, ph, c, OPP[q]).bounce) {
+          Af[at(OPP[q], c.idx)] = of[q];
+          Ag[at(OPP[q], c.idx)] = og[q];
+        }
+        // readers whose pull of q is clamped onto this cell
+        if (ft >= 0 && q > 0) {
+          const size_t k = (size_t)ft * (Q - 1) + (q - 1);
+          if (ftgt[k] >= 0)
+            for (int m = 0; m < 7; ++m) {
+              const int ri = frd[k * 7 + m];
+              if (ri >= 0) {
+                Af[at(q, ri)] = of[q];
+                Ag[at(q, ri)] = og[q];
+              }
+            }
+        }
+      }
+    }
+  }
+  count_lanes(bad, counters, 0);
 }
 
 }  // namespace rlb

@@ -50,6 +50,10 @@ struct rlb_solver {
   double *d_omega_cell;       // per-cell 1/tau of a tau field (or null)
   double *d_dtau_cell;        // per-cell dL/dtau(x) accumulated by the reverse steps
   unsigned long long *d_bad;  // validation counter of rlb_set_tau_field
+  bool inplace;               // one state buffer, AA-pattern streaming
+  int aa_phase;               // 0: swapped layout (S_t readable), 1: streamed layout
+  void *d_fb;                 // face copies of the in-place layout
+  FaceMap fm;
 };
 
 namespace {
@@ -137,6 +141,7 @@ rlb_status validate(const rlb_params *p, long long *cells_out) {
   }
   if (!(p->kappa == 0.0 || (p->kappa > 0.0 && p->kappa <= 1.0)))
     return fail(RLB_EINVAL, "kappa (P = kappa e) must be in (0, 1], or 0 for 1/3");
+  if (p->inplace != 0 && p->inplace != 1) return fail(RLB_EINVAL, "inplace must be 0 or 1");
   *cells_out = cells;
   return RLB_OK;
 }
@@ -215,6 +220,9 @@ rlb_status launch_init(rlb_solver *h, const double *n0, const double *e0, const 
                      (El *)h->d_in_eq);
   hipLaunchKernelGGL((k_init<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
                      n0, e0, beta0, (El *)h->pop[0], (El *)h->pop[1], (const El *)h->d_in_eq);
+  if (h->inplace)
+    hipLaunchKernelGGL((k_aa_swap<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+                       h->ph, h->fm, (El *)h->pop[0], (El *)h->d_fb);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -231,6 +239,21 @@ template <int ST, class TC>
 rlb_status launch_steps(rlb_solver *h, int nsteps) {
   using El = typename Codec<ST, TC>::elem;
   const HeldEq<El> in_eq = held_eq<El>(h);
+  if (h->inplace) {
+    El *A = (El *)h->pop[0];
+    for (int s = 0; s < nsteps; ++s) {
+      if (h->aa_phase == 0)
+        hipLaunchKernelGGL((k_aa_pull<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream,
+                           h->g, h->ph, h->fm, A, (const El *)h->d_fb, (const int *)h->d_ftgt,
+                           (const int *)h->d_frd, in_eq, h->d_counters);
+      else
+        hipLaunchKernelGGL((k_aa_local<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream,
+                           h->g, h->ph, h->fm, A, (El *)h->d_fb, in_eq, h->d_counters);
+      h->aa_phase = 1 - h->aa_phase;
+    }
+    RLB_HIP(hipGetLastError());
+    return RLB_OK;
+  }
   for (int s = 0; s < nsteps; ++s) {
     const El *src = (const El *)h->pop[h->cur];
     El *dst = (El *)h->pop[1 - h->cur];
@@ -273,7 +296,7 @@ rlb_status launch_transport(rlb_solver *h, double *T, double *ent, double *eta, 
   using El = typename Codec<ST, TC>::elem;
   const El *S = (const El *)h->pop[h->cur];
   hipLaunchKernelGGL((k_transport<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
-                     h->ph, S, S + (size_t)Q * h->g.qs, T, ent, eta, eos);
+                     h->ph, S, S + (size_t)Q * h->g.qs, T, ent, eta, eos, h->inplace ? 1 : 0);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -283,7 +306,8 @@ rlb_status launch_moments(rlb_solver *h, double *n, double *e, double *beta, boo
   using El = typename Codec<ST, TC>::elem;
   const El *S = (const El *)h->pop[h->cur];
   hipLaunchKernelGGL((k_moments<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
-                     S, S + (size_t)Q * h->g.qs, n, e, beta, sums ? h->d_part : nullptr);
+                     S, S + (size_t)Q * h->g.qs, n, e, beta, sums ? h->d_part : nullptr,
+                     h->inplace ? 1 : 0);
   if (sums)
     hipLaunchKernelGGL(k_finish, dim3(h->p.batch), dim3(BLOCK), 0, h->stream, h->d_part,
                        h->g.nblk_per, (const double *)nullptr, (const int *)nullptr, h->d_res,
@@ -297,7 +321,7 @@ rlb_status launch_fields_g(rlb_solver *h, const void *Sg, double *e, double *bet
   using El = typename Codec<ST, TC>::elem;
   hipLaunchKernelGGL((k_moments<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
                      (const El *)nullptr, (const El *)Sg, (double *)nullptr, e, beta,
-                     (double *)nullptr);
+                     (double *)nullptr, 0);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -305,6 +329,18 @@ rlb_status launch_fields_g(rlb_solver *h, const void *Sg, double *e, double *bet
 // Cells of the general reverse kernel, in index order, each instance padded to
 // whole workgroups (-1 entries), so that every workgroup's partial sums belong
 // to one instance and their reduction order is fixed.
+// Face-reader table (once per solver): readers whose pulls clamp onto face cells.
+rlb_status build_faces_table(rlb_solver *h) {
+  if (h->faces.count == 0 || h->d_ftgt) return RLB_OK;
+  const long long nf = h->faces.start[h->faces.count];
+  RLB_HIP(hipMalloc(&h->d_ftgt, (size_t)nf * (Q - 1) * sizeof(int)));
+  RLB_HIP(hipMalloc(&h->d_frd, (size_t)nf * (Q - 1) * 7 * sizeof(int)));
+  hipLaunchKernelGGL(k_faces_table, dim3((unsigned)((nf + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                     h->stream, h->g, h->ph, h->faces, h->d_ftgt, h->d_frd);
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
+}
+
 rlb_status build_adjoint_list(rlb_solver *h) {
   const size_t cells = (size_t)h->g.per * h->p.batch;
   uint8_t *d_flag = nullptr;
@@ -344,13 +380,9 @@ rlb_status build_adjoint_list(rlb_solver *h) {
                        h->d_gsrcq, h->d_ginfo);
     RLB_HIP(hipGetLastError());
   }
-  if (h->faces.count > 0) {
-    const long long nf = h->faces.start[h->faces.count];
-    RLB_HIP(hipMalloc(&h->d_ftgt, (size_t)nf * (Q - 1) * sizeof(int)));
-    RLB_HIP(hipMalloc(&h->d_frd, (size_t)nf * (Q - 1) * 7 * sizeof(int)));
-    hipLaunchKernelGGL(k_faces_table, dim3((unsigned)((nf + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
-                       h->stream, h->g, h->ph, h->faces, h->d_ftgt, h->d_frd);
-    RLB_HIP(hipGetLastError());
+  {
+    rlb_status st = build_faces_table(h);
+    if (st != RLB_OK) return st;
   }
   h->glist_total = (int)list.size();
   h->glist_ready = true;
@@ -475,6 +507,7 @@ void free_solver(rlb_solver *h) {
   if (h->d_omega_cell) (void)hipFree(h->d_omega_cell);
   if (h->d_dtau_cell) (void)hipFree(h->d_dtau_cell);
   if (h->d_bad) (void)hipFree(h->d_bad);
+  if (h->d_fb) (void)hipFree(h->d_fb);
   delete h;
 }
 
@@ -506,9 +539,10 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
   long long cells = 0;
   rlb_status s = validate(p, &cells);
   if (s != RLB_OK) return s;
-  if (!tau || !n0 || !e0 || !beta0 || !pop_a || !pop_b)
+  const bool inplace = p->inplace != 0;
+  if (!tau || !n0 || !e0 || !beta0 || !pop_a || (!inplace && !pop_b))
     return fail(RLB_EINVAL, "a required pointer is NULL");
-  if (pop_a == pop_b) return fail(RLB_EINVAL, "pop_a and pop_b must differ");
+  if (!inplace && pop_a == pop_b) return fail(RLB_EINVAL, "pop_a and pop_b must differ");
   for (int b = 0; b < p->batch; ++b)
     if (!(tau[b] > 0.5) || !std::isfinite(tau[b]))
       return fail(RLB_EINVAL, "tau must be > 1/2 (positive viscosity) for every instance");
@@ -521,7 +555,9 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
   h->elem = elem_size(p->storage);
   h->lam_elem = sizeof(LamT);
   h->pop[0] = pop_a;
-  h->pop[1] = pop_b;
+  h->pop[1] = inplace ? pop_a : pop_b;  // the in-place layout uses pop_a only
+  h->inplace = inplace;
+  h->aa_phase = 0;
   h->cur = 0;
   h->stream = (hipStream_t)stream;
   setup_geometry(h);
@@ -600,6 +636,21 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
   }
   ph.omega = h->d_omega;
   h->held = solid != nullptr || h->g.any_inflow != 0;
+  if (inplace) {
+    FaceMap &fm = h->fm;
+    for (int a = 0; a < 3; ++a) fm.id[a][0] = fm.id[a][1] = -1;
+    for (int f = 0; f < h->faces.count; ++f) fm.id[h->faces.axis[f]][h->faces.side[f]] = f;
+    for (int f = 0; f <= h->faces.count; ++f) fm.start[f] = h->faces.start[f];
+    fm.count = h->faces.count;
+    fm.nf = h->faces.start[h->faces.count];
+    if (fm.nf > 0 &&
+        (e = hipMalloc(&h->d_fb, (size_t)2 * Q * fm.nf * h->elem)) != hipSuccess)
+      return cleanup_fail(e, "hipMalloc(face copies)");
+    if ((s = build_faces_table(h)) != RLB_OK) {
+      free_solver(h);
+      return s;
+    }
+  }
   auto launch = [&]() -> rlb_status { RLB_DISPATCH(h, launch_init, h, n0, e0, beta0); };
   s = launch();
   if (s == RLB_OK && (e = hipStreamSynchronize(h->stream)) != hipSuccess)
@@ -623,6 +674,7 @@ rlb_status rlb_step(rlb_solver *h, int32_t nsteps) {
 
 rlb_status rlb_step_g(rlb_solver *h, const void *g_src, void *g_dst) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
   if (h->ph.eta_s > 0.0)
     return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   if (!g_src || !g_dst || g_src == g_dst) return fail(RLB_EINVAL, "g_src/g_dst invalid");
@@ -638,6 +690,8 @@ rlb_status rlb_current(rlb_solver *h, void **state) {
 
 rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double *sums) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->inplace && h->aa_phase != 0)
+    return fail(RLB_EINVAL, "in-place layout after an odd number of steps: S_t is not stored");
   auto launch = [&]() -> rlb_status {
     RLB_DISPATCH(h, launch_moments, h, n, e, beta, sums != nullptr);
   };
@@ -651,6 +705,7 @@ rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double
 
 rlb_status rlb_fields_g(rlb_solver *h, const void *g_state, double *e, double *beta) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
   if (!g_state || (!e && !beta)) return fail(RLB_EINVAL, "g_state or outputs invalid");
   RLB_DISPATCH(h, launch_fields_g, h, g_state, e, beta);
 }
@@ -686,6 +741,7 @@ rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *la
                             void *lam_out, double *dL_dtau, double *dL_dbeta_in,
                             double *dL_de_in) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
   if (h->ph.gen_eos)
     return fail(RLB_EINVAL, "the reverse mode is built for e = 3P (kappa = 1/3)");
   if (h->ph.eta_s > 0.0)
@@ -706,6 +762,7 @@ rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *la
 rlb_status rlb_adjoint_sweep(rlb_solver *h, const void *g_seq, int64_t seq_stride, int32_t n,
                              void *lam_a, void *lam_b, void **lam_result) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
   if (h->ph.gen_eos)
     return fail(RLB_EINVAL, "the reverse mode is built for e = 3P (kappa = 1/3)");
   if (h->ph.eta_s > 0.0)
@@ -739,6 +796,7 @@ rlb_status rlb_adjoint_flush(rlb_solver *h, double *dL_dtau, double *dL_dbeta_in
 
 rlb_status rlb_advance_g(rlb_solver *h, const void *g_src, void *g_dst, void *g_tmp, int32_t n) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
   if (h->ph.eta_s > 0.0)
     return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   if (n < 0 || !g_src || !g_dst || g_src == g_dst || (n > 1 && (!g_tmp || g_tmp == g_src ||
@@ -762,6 +820,7 @@ rlb_status rlb_advance_g(rlb_solver *h, const void *g_src, void *g_dst, void *g_
 
 rlb_status rlb_trajectory_g(rlb_solver *h, void *g_seq, int64_t seq_stride, int32_t n) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
   if (h->ph.eta_s > 0.0)
     return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   const int64_t need = (int64_t)Q * h->g.qs * (int64_t)h->elem;
@@ -779,6 +838,7 @@ rlb_status rlb_trajectory_g(rlb_solver *h, void *g_seq, int64_t seq_stride, int3
 rlb_status rlb_moments_adjoint(rlb_solver *h, const void *g_state_T, const double *dL_de,
                                const double *dL_dbeta, void *lam_T) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
   if (h->ph.gen_eos)
     return fail(RLB_EINVAL, "the reverse mode is built for e = 3P (kappa = 1/3)");
   if (!g_state_T || !dL_de || !dL_dbeta || !lam_T)
@@ -790,6 +850,7 @@ rlb_status rlb_init_adjoint(rlb_solver *h, const double *e0, const double *beta0
                             const void *lam_0, double *dL_de0, double *dL_dbeta0,
                             double *dL_dbeta_in, double *dL_de_in) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
   if (h->ph.gen_eos)
     return fail(RLB_EINVAL, "the reverse mode is built for e = 3P (kappa = 1/3)");
   if (!e0 || !beta0 || !lam_0 || !dL_de0 || !dL_dbeta0)
@@ -847,6 +908,8 @@ rlb_status rlb_hold_eta_over_s(rlb_solver *h, double eta_over_s, double d_G) {
     return fail(RLB_EINVAL, "eta_over_s must be >= 0 and d_G > 0 (both finite)");
   if (h->ph.gen_eos && eta_over_s > 0.0)
     return fail(RLB_EINVAL, "transport quantities and the eta/s rule are defined for e = 3P (kappa = 1/3)");
+  if (h->inplace && eta_over_s > 0.0)
+    return fail(RLB_EINVAL, "holding eta/s is built for the two-buffer layout (inplace = 0)");
   h->ph.eta_s = eta_over_s;
   h->ph.d_G = d_G;
   return RLB_OK;
@@ -855,6 +918,8 @@ rlb_status rlb_hold_eta_over_s(rlb_solver *h, double eta_over_s, double d_G) {
 rlb_status rlb_transport(rlb_solver *h, double d_G, double *T, double *s, double *eta,
                          double *eta_over_s) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->inplace && h->aa_phase != 0)
+    return fail(RLB_EINVAL, "in-place layout after an odd number of steps: S_t is not stored");
   if (h->ph.gen_eos)
     return fail(RLB_EINVAL, "transport quantities and the eta/s rule are defined for e = 3P (kappa = 1/3)");
   if (!(d_G > 0.0) || !std::isfinite(d_G)) return fail(RLB_EINVAL, "d_G must be > 0");

@@ -28,7 +28,7 @@ def _ptr(t: Optional[torch.Tensor]):
 
 def make_params(nx, ny, nz, batch=1, c_l=1.0, bc=((0, 0), (0, 0), (0, 0)),
                 inflow=(1.0, 1.0, 0.0, 0.0, 0.0), storage=_lib.F64, n_ref=1.0,
-                e_ref=1.0, collide=_lib.COLLIDE_AUTO, kappa=0.0) -> _lib.Params:
+                e_ref=1.0, collide=_lib.COLLIDE_AUTO, kappa=0.0, inplace=False) -> _lib.Params:
     p = _lib.Params()
     p.nx, p.ny, p.nz, p.batch = int(nx), int(ny), int(nz), int(batch)
     p.c_l = float(c_l)
@@ -42,7 +42,19 @@ def make_params(nx, ny, nz, batch=1, c_l=1.0, bc=((0, 0), (0, 0), (0, 0)),
     p.n_ref, p.e_ref = float(n_ref), float(e_ref)
     p.collide = int(collide)
     p.kappa = float(kappa)
+    p.inplace = 1 if inplace else 0
     return p
+
+
+def _lattice_tables():
+    """(e[19][3], w[19], opp[19]) of the D3Q19 ordering the library uses
+    (0 rest; +x,-x,+y,-y,+z,-z; then the xy, xz, yz diagonal pairs)."""
+    e = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+         (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1),
+         (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
+    opp = [e.index(tuple(-v for v in d)) for d in e]
+    w = [1 / 3 if sum(map(abs, d)) == 0 else (1 / 18 if sum(map(abs, d)) == 1 else 1 / 36) for d in e]
+    return e, w, opp
 
 
 def unpack_block(t: torch.Tensor, cells: int) -> torch.Tensor:
@@ -85,7 +97,8 @@ class Solver:
         self.setup = s
         self.params = make_params(s.nx, s.ny, s.nz, s.batch, s.c_l, s.bc, s.inflow, s.storage,
                                   s.n_ref, s.e_ref, getattr(s, "collide", _lib.COLLIDE_AUTO),
-                                  getattr(s, "kappa", 0.0))
+                                  getattr(s, "kappa", 0.0), getattr(s, "inplace", False))
+        self.inplace = bool(getattr(s, "inplace", False))
         self.nx, self.ny, self.nz, self.batch = s.nx, s.ny, s.nz, s.batch
         self.cells = s.batch * s.nz * s.ny * s.nx
         self.storage = int(s.storage)
@@ -95,7 +108,7 @@ class Solver:
         self.nbrick = self.q_stride // BRICK
         with torch.cuda.stream(self.stream):
             self.pop = [torch.empty((2, self.nbrick, Q, BRICK), dtype=self.dtype,
-                                    device=self.device) for _ in range(2)]
+                                    device=self.device) for _ in range(1 if self.inplace else 2)]
             f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(self.device)
             n0 = f64(np.asarray(s.n0).reshape(-1))
             e0 = f64(np.asarray(s.e0).reshape(-1))
@@ -111,7 +124,7 @@ class Solver:
         check(_lib.lib().rlb_init(ctypes.byref(h), ctypes.byref(self.params),
                                   self.tau.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   _ptr(self.solid), _ptr(n0), _ptr(e0), _ptr(b0),
-                                  _ptr(self.pop[0]), _ptr(self.pop[1]),
+                                  _ptr(self.pop[0]), _ptr(self.pop[-1]) if not self.inplace else None,
                                   ctypes.c_void_p(self.stream.cuda_stream)), "rlb_init")
         self.h = h
         self.tau_cell = None
@@ -208,6 +221,15 @@ class Solver:
             if t.data_ptr() == p.value:
                 return t
         raise RuntimeError("current state is not one of the solver's buffers")
+
+    def populations(self) -> torch.Tensor:
+        """The current stored state S_t as [2][19][cells] in the natural slot
+        order (a copy; the in-place layout is un-swapped)."""
+        st = self.unpack(self.state())
+        if self.inplace:
+            _, _, opp = _lattice_tables()
+            st = st[:, opp]
+        return st
 
     def g_state(self) -> torch.Tensor:
         return self.state()[1]

@@ -61,6 +61,7 @@ class Setup:
     eta_s: float = 0.0  # > 0: hold eta/s fixed (tau from the local state)
     d_G: float = 16.0  # degeneracy in n_eq = d_G T^3 / pi^2
     kappa: float = 1.0 / 3.0  # equation of state P = kappa e
+    inplace: bool = False  # one state buffer, in-place (AA-pattern) streaming
 
     @property
     def cells(self) -> int:

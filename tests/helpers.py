@@ -40,4 +40,4 @@ def oracle_fields(s: ri.Setup, steps: int):
 
 def gpu_state(solver) -> np.ndarray:
     """Current GPU state as float64 [2][19][cells] (undeviated storages only)."""
-    return solver.unpack(solver.state()).double().cpu().numpy()
+    return solver.populations().double().cpu().numpy()
