@@ -150,9 +150,9 @@ __device__ __forceinline__ int xcd_remap(int B, int nblk) {
   return k * per + min(k, rem) + i;
 }
 
-__device__ __forceinline__ Cell decode_cell(const Geom &g) {
+__device__ __forceinline__ Cell decode_cell(const Geom &g, int B = -1) {
   Cell c;
-  c.L = xcd_remap((int)blockIdx.x, g.nblk);
+  c.L = xcd_remap(B < 0 ? (int)blockIdx.x : B, g.nblk);
   c.b = (int)fdiv(g.div_blk, (uint32_t)c.L);
   c.local = (c.L - c.b * g.nblk_per) * BLOCK + (int)threadIdx.x;
   c.active = c.local < g.per;
@@ -1326,7 +1326,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify(const Geom g, const uint8_t 
 // itself; representation "streamed": A holds the pulled, pre-collision
 // value P(x)_q = S(source_q(x)) at slot q of x.
 //   k_aa_local  (streamed -> swapped): collide in place at the own cell.
-//   k_aa_pull   (swapped -> streamed): pull, collide, and push every
+//   k_aa_pull_all (swapped -> streamed): pull, collide, and push every
 //     post-collision S(x)_q to each cell that will pull it: the plain
 //     neighbour x + e_q, x itself (slot opp(q)) when x's pull of opp(q)
 //     bounces off a solid, and the readers whose pull of q is clamped onto
@@ -1348,6 +1348,37 @@ __device__ __forceinline__ long long face_pos(const Geom &g, const FaceMap &fm, 
   const int co[3] = {x, y, z};
   const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
   return fm.start[f] + ((long long)b * g.n[v] + co[v]) * g.n[u] + co[u];
+}
+
+// Relax both populations of one update with the same arithmetic as k_step
+// and hand each post-collision value to sg(q, v) / sf(q, v) as soon as it is
+// formed (g first, then f), so that the pre-collision values die early;
+// returns whether the update was unphysical.
+template <class Cd, class SG, class SF>
+__device__ __forceinline__ bool collide_emit(const Phys &ph, const Cell &c,
+                                             const typename Cd::calc (&pg)[Q],
+                                             const typename Cd::calc (&pf)[Q], const SG &sg,
+                                             const SF &sf) {
+  using T = typename Cd::calc;
+  T sE = (T)0, sx, sy, sz;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) sE += pg[q];
+  mirror_sums(pg, sx, sy, sz);
+  const Inv iv = invert(ph, ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
+                        ph.c * (double)sz);
+  EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
+  const T om = (T)omega_of(ph, c.b, c.idx);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) sg(q, Cd::enc(pg[q] + om * (geq_dev(k, q) - pg[q])));
+  T sN = (T)0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) sN += pf[q];
+  const double N = ph.n_ref + (double)sN;
+  k.N = (T)N;
+  k.Nd = (T)(N - ph.n_ref);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) sf(q, Cd::enc(pf[q] + om * (feq_dev(k, q) - pf[q])));
+  return iv.bad;
 }
 
 // Relax both populations of one update in place (pre -> post) with the same
@@ -1410,6 +1441,47 @@ __global__ __launch_bounds__(BLOCK) void k_aa_swap(const Geom g, const Phys ph, 
   }
 }
 
+// Cells of the in-place pull kernel's fast path: no solid neighbour, not an
+// inflow cell, and off every face of a non-periodic axis (pulls and pushes
+// then reach plain neighbours only; pushes into an inflow cell's slots are
+// overwritten by its held values at the next local step, so the layer next
+// to an inflow plane is plain too).
+__device__ __forceinline__ bool aa_plain(const Geom &g, const Phys &ph, const Cell &c) {
+  const uint8_t cls = ph.cls ? ph.cls[c.idx] : (uint8_t)0;
+  if ((cls & (CLS_SOLID | CLS_NEAR)) || is_inflow(g, c.x, c.y, c.z)) return false;
+  const int co[3] = {c.x, c.y, c.z};
+  for (int a = 0; a < 3; ++a)
+    if (!g.periodic[a] && (co[a] < 1 || co[a] > g.n[a] - 2)) return false;
+  return true;
+}
+
+// flag[cell] = 1 for the non-solid cells off the fast path (the host lists them).
+__global__ __launch_bounds__(BLOCK) void k_mark_aa(const Geom g, const Phys ph,
+                                                   uint8_t *__restrict__ flag) {
+  const Cell c = decode_cell(g);
+  if (!c.active) return;
+  flag[c.idx] = (!solid_at(ph, c.idx) && !aa_plain(g, ph, c)) ? (uint8_t)1 : (uint8_t)0;
+}
+
+// Face copies of one cell's post-collision values (one per non-periodic face
+// the cell lies on).
+template <class El, class VF, class VG>
+__device__ __forceinline__ void aa_face_copies(const Geom &g, const FaceMap &fm, const Cell &c,
+                                               El *__restrict__ Fb, const VF &of, const VG &og) {
+  const int co[3] = {c.x, c.y, c.z};
+  for (int a = 0; a < 3; ++a) {
+    if (g.periodic[a]) continue;
+    const int sd = co[a] == 0 ? 0 : (co[a] == g.n[a] - 1 ? 1 : -1);
+    if (sd < 0) continue;
+    const long long t = face_pos(g, fm, fm.id[a][sd], a, c.b, c.x, c.y, c.z);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      Fb[(size_t)q * fm.nf + t] = of(q);
+      Fb[(size_t)(Q + q) * fm.nf + t] = og(q);
+    }
+  }
+}
+
 template <int ST, class TC>
 __global__ __launch_bounds__(BLOCK) void k_aa_local(const Geom g, const Phys ph, const FaceMap fm,
                                                     typename Codec<ST, TC>::elem *__restrict__ A,
@@ -1425,14 +1497,16 @@ __global__ __launch_bounds__(BLOCK) void k_aa_local(const Geom g, const Phys ph,
     const size_t qs = (size_t)g.qs;
     El *__restrict__ Af = A;
     El *__restrict__ Ag = A + Q * qs;
-    const bool inflow = is_inflow(g, c.x, c.y, c.z);
-    El of[Q], og[Q];
-    if (inflow) {
+    const bool face = fm.count > 0 && !aa_plain(g, ph, c);
+    if (is_inflow(g, c.x, c.y, c.z)) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        of[q] = in_eq.v[q];
-        og[q] = in_eq.v[Q + q];
+        Af[at(OPP[q], c.idx)] = in_eq.v[q];
+        Ag[at(OPP[q], c.idx)] = in_eq.v[Q + q];
       }
+      if (face)
+        aa_face_copies(g, fm, c, Fb, [&](int q) { return in_eq.v[q]; },
+                       [&](int q) { return in_eq.v[Q + q]; });
     } else {
       T pf[Q], pg[Q];
 #pragma unroll
@@ -1440,167 +1514,168 @@ __global__ __launch_bounds__(BLOCK) void k_aa_local(const Geom g, const Phys ph,
         pf[q] = Cd::dec(Af[at(q, c.idx)]);
         pg[q] = Cd::dec(Ag[at(q, c.idx)]);
       }
-      bad = collide_inplace<Cd>(g, ph, c, pg, pf);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        of[q] = Cd::enc(pf[q]);
-        og[q] = Cd::enc(pg[q]);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      Af[at(OPP[q], c.idx)] = of[q];
-      Ag[at(OPP[q], c.idx)] = og[q];
-    }
-    const int co[3] = {c.x, c.y, c.z};
-    for (int a = 0; a < 3; ++a) {
-      if (g.periodic[a]) continue;
-      const int side = co[a] == 0 ? 0 : (co[a] == g.n[a] - 1 ? 1 : -1);
-      for (int sd = 0; sd < 2; ++sd) {
-        if (side != sd) continue;
-        const long long t = face_pos(g, fm, fm.id[a][sd], a, c.b, c.x, c.y, c.z);
-        for (int q = 0; q < Q; ++q) {
-          Fb[(size_t)q * fm.nf + t] = of[q];
-          Fb[(size_t)(Q + q) * fm.nf + t] = og[q];
-        }
-      }
+      bad = collide_emit<Cd>(
+          ph, c, pg, pf, [&](int q, El v) { Ag[at(OPP[q], c.idx)] = v; },
+          [&](int q, El v) { Af[at(OPP[q], c.idx)] = v; });
+      // face cells copy what they just stored (same thread: reads see the writes)
+      if (face)
+        aa_face_copies(g, fm, c, Fb, [&](int q) { return Af[at(OPP[q], c.idx)]; },
+                       [&](int q) { return Ag[at(OPP[q], c.idx)]; });
     }
   }
   count_lanes(bad, counters, 0);
 }
 
+// In-place pull step of one updated cell on the general path (listed cells:
+// near a solid, inflow, or on a face of a non-periodic axis).
+template <class Cd>
+__device__ __forceinline__ bool aa_pull_general(const Geom &g, const Phys &ph, const FaceMap &fm,
+                                                typename Cd::elem *__restrict__ A,
+                                                const typename Cd::elem *__restrict__ Fb,
+                                                const int *__restrict__ ftgt,
+                                                const int *__restrict__ frd,
+                                                const HeldEq<typename Cd::elem> &in_eq,
+                                                const Cell &c) {
+  using T = typename Cd::calc;
+  using El = typename Cd::elem;
+  const size_t qs = (size_t)g.qs;
+  El *__restrict__ Af = A;
+  El *__restrict__ Ag = A + Q * qs;
+  const bool inflow = is_inflow(g, c.x, c.y, c.z);
+  const int co[3] = {c.x, c.y, c.z};
+  bool bad = false;
+  T pf[Q], pg[Q];
+  if (inflow) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      pf[q] = Cd::dec(in_eq.v[q]);
+      pg[q] = Cd::dec(in_eq.v[Q + q]);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const Pull p = pull_general(g, ph, c, q);
+      // the first clamped axis names the face copy to read
+      int a = -1, sd = 0;
+#pragma unroll
+      for (int k = 2; k >= 0; --k) {
+        const int e = k == 0 ? EX[q] : (k == 1 ? EY[q] : EZ[q]);
+        const int r = co[k] - e;
+        if (!g.periodic[k] && (r < 0 || r >= g.n[k])) {
+          a = k;
+          sd = r < 0 ? 0 : 1;
+        }
+      }
+      if (p.clamped && !p.bounce && a >= 0) {  // bounce-back takes precedence
+        const long long rem = p.idx - (long long)c.b * g.per;
+        const int sx = (int)(rem % g.n[0]);
+        const int sy = (int)((rem / g.n[0]) % g.n[1]);
+        const int sz = (int)(rem / ((long long)g.n[0] * g.n[1]));
+        const long long t = face_pos(g, fm, fm.id[a][sd], a, c.b, sx, sy, sz);
+        pf[q] = Cd::dec(Fb[(size_t)q * fm.nf + t]);
+        pg[q] = Cd::dec(Fb[(size_t)(Q + q) * fm.nf + t]);
+      } else {
+        // plain source: S(src)_q sits at slot opp(q); bounce-back
+        // (p.idx = c.idx, p.q = opp(q)): S(x)_opp(q) sits at slot q
+        const size_t o = at(OPP[p.q], p.idx);
+        pf[q] = Cd::dec(Af[o]);
+        pg[q] = Cd::dec(Ag[o]);
+      }
+    }
+    bad = collide_inplace<Cd>(g, ph, c, pg, pf);
+  }
+  // this cell's entry in the face-reader table (first face listing it)
+  long long ft = -1;
+  for (int f = 0; f < fm.count && ft < 0; ++f)
+    for (int a = 0; a < 3; ++a)
+      for (int sd = 0; sd < 2; ++sd)
+        if (fm.id[a][sd] == f && co[a] == (sd == 0 ? 0 : g.n[a] - 1))
+          ft = face_pos(g, fm, f, a, c.b, c.x, c.y, c.z);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const El vf = inflow ? in_eq.v[q] : Cd::enc(pf[q]);
+    const El vg = inflow ? in_eq.v[Q + q] : Cd::enc(pg[q]);
+    // plain receiver x + e_q
+    int r[3];
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int e = a == 0 ? EX[q] : (a == 1 ? EY[q] : EZ[q]);
+      r[a] = co[a] + e;
+      if (g.periodic[a]) {
+        if (r[a] < 0) r[a] += g.n[a];
+        if (r[a] >= g.n[a]) r[a] -= g.n[a];
+      } else if (r[a] < 0 || r[a] >= g.n[a]) {
+        in = false;
+      }
+    }
+    if (in) {
+      const long long ri = cell_index(g, c.b, r[0], r[1], r[2]);
+      if (!solid_at(ph, ri) && !is_inflow(g, r[0], r[1], r[2])) {
+        Af[at(q, ri)] = vf;
+        Ag[at(q, ri)] = vg;
+      }
+    }
+    // bounce-back receiver: this cell, when its pull of opp(q) hits a solid
+    if (!inflow && pull_general(g, ph, c, OPP[q]).bounce) {
+      Af[at(OPP[q], c.idx)] = vf;
+      Ag[at(OPP[q], c.idx)] = vg;
+    }
+    // readers whose pull of q is clamped onto this cell
+    if (ft >= 0 && q > 0) {
+      const size_t k = (size_t)ft * (Q - 1) + (q - 1);
+      if (ftgt[k] >= 0)
+        for (int m = 0; m < 7; ++m) {
+          const int ri = frd[k * 7 + m];
+          if (ri >= 0) {
+            Af[at(q, ri)] = vf;
+            Ag[at(q, ri)] = vg;
+          }
+        }
+    }
+  }
+  return bad;
+}
+
+// In-place pull step in one launch: the first nlist workgroups (a multiple
+// of 8, so that the rest keep their XCD placement) take the listed cells on
+// the general path, the others the fast path; the two sets of cells touch
+// disjoint locations of A, and the latency-bound listed work overlaps the
+// streaming work.
 template <int ST, class TC>
-__global__ __launch_bounds__(BLOCK) void k_aa_pull(const Geom g, const Phys ph, const FaceMap fm,
-                                                   typename Codec<ST, TC>::elem *__restrict__ A,
-                                                   const typename Codec<ST, TC>::elem *__restrict__ Fb,
-                                                   const int *__restrict__ ftgt,
-                                                   const int *__restrict__ frd,
-                                                   const HeldEq<typename Codec<ST, TC>::elem> in_eq,
-                                                   unsigned long long *__restrict__ counters) {
+__global__ __launch_bounds__(BLOCK) void k_aa_pull_all(const Geom g, const Phys ph,
+                                                       const FaceMap fm, int nlist,
+                                                       const int *__restrict__ list,
+                                                       typename Codec<ST, TC>::elem *__restrict__ A,
+                                                       const typename Codec<ST, TC>::elem *__restrict__ Fb,
+                                                       const int *__restrict__ ftgt,
+                                                       const int *__restrict__ frd,
+                                                       const HeldEq<typename Codec<ST, TC>::elem> in_eq,
+                                                       unsigned long long *__restrict__ counters) {
   using Cd = Codec<ST, TC>;
   using T = typename Cd::calc;
   using El = typename Cd::elem;
-  const Cell c = decode_cell(g);
   bool bad = false;
-  if (c.active && !solid_at(ph, c.idx)) {
-    const size_t qs = (size_t)g.qs;
-    El *__restrict__ Af = A;
-    El *__restrict__ Ag = A + Q * qs;
-    const bool inflow = is_inflow(g, c.x, c.y, c.z);
-    const bool plain = adjoint_plain(g, ph, c);
-    const FaceCorr fc = face_corr(g, c);
-    El of[Q], og[Q];
-    if (inflow) {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        of[q] = in_eq.v[q];
-        og[q] = in_eq.v[Q + q];
-      }
-    } else {
+  if ((int)blockIdx.x < nlist) {
+    const int li = list[(size_t)blockIdx.x * BLOCK + threadIdx.x];
+    if (li >= 0) bad = aa_pull_general<Cd>(g, ph, fm, A, Fb, ftgt, frd, in_eq, cell_at(g, li));
+  } else {
+    const Cell c = decode_cell(g, (int)blockIdx.x - nlist);
+    if (c.active && aa_plain(g, ph, c)) {
+      const size_t qs = (size_t)g.qs;
+      El *__restrict__ Af = A;
+      El *__restrict__ Ag = A + Q * qs;
+      const FaceCorr fc = face_corr(g, c);
       T pf[Q], pg[Q];
-      if (plain) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const size_t o = at(OPP[q], src_fast(g, c, fc, q));
-          pf[q] = Cd::dec(Af[o]);
-          pg[q] = Cd::dec(Ag[o]);
-        }
-      } else {
-        for (int q = 0; q < Q; ++q) {
-          const Pull p = pull_general(g, ph, c, q);
-          // the first clamped axis names the face copy to read
-          const int co[3] = {c.x, c.y, c.z};
-          const int e[3] = {EX[q], EY[q], EZ[q]};
-          int a = -1, sd = 0;
-          for (int k = 2; k >= 0; --k) {
-            if (g.periodic[k]) continue;
-            const int r = co[k] - e[k];
-            if (r < 0 || r >= g.n[k]) {
-              a = k;
-              sd = r < 0 ? 0 : 1;
-            }
-          }
-          if (p.clamped && !p.bounce && a >= 0) {  // bounce-back takes precedence
-            const long long src = p.idx;
-            const long long rem = src - (long long)c.b * g.per;
-            const int sx = (int)(rem % g.n[0]);
-            const int sy = (int)((rem / g.n[0]) % g.n[1]);
-            const int sz = (int)(rem / ((long long)g.n[0] * g.n[1]));
-            const long long t = face_pos(g, fm, fm.id[a][sd], a, c.b, sx, sy, sz);
-            pf[q] = Cd::dec(Fb[(size_t)q * fm.nf + t]);
-            pg[q] = Cd::dec(Fb[(size_t)(Q + q) * fm.nf + t]);
-          } else {
-            // plain source: S(src)_q sits at slot opp(q); bounce-back
-            // (p.idx = c.idx, p.q = opp(q)): S(x)_opp(q) sits at slot q
-            const size_t o = at(OPP[p.q], p.idx);
-            pf[q] = Cd::dec(Af[o]);
-            pg[q] = Cd::dec(Ag[o]);
-          }
-        }
-      }
-      bad = collide_inplace<Cd>(g, ph, c, pg, pf);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        of[q] = Cd::enc(pf[q]);
-        og[q] = Cd::enc(pg[q]);
+        const size_t o = at(OPP[q], src_fast(g, c, fc, q));
+        pf[q] = Cd::dec(Af[o]);
+        pg[q] = Cd::dec(Ag[o]);
       }
-    }
-    if (plain) {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const size_t o = at(q, src_fast(g, c, fc, OPP[q]));  // x + e_q
-        Af[o] = of[q];
-        Ag[o] = og[q];
-      }
-    } else {
-      const int co[3] = {c.x, c.y, c.z};
-      // this cell's entry in the face-reader table (first face listing it)
-      long long ft = -1;
-      for (int f = 0; f < fm.count && ft < 0; ++f) {
-        for (int a = 0; a < 3; ++a)
-          for (int sd = 0; sd < 2; ++sd)
-            if (fm.id[a][sd] == f && co[a] == (sd == 0 ? 0 : g.n[a] - 1))
-              ft = face_pos(g, fm, f, a, c.b, c.x, c.y, c.z);
-      }
-      for (int q = 0; q < Q; ++q) {
-        // plain receiver x + e_q
-        int r[3];
-        bool in = true;
-        for (int a = 0; a < 3; ++a) {
-          const int e = a == 0 ? EX[q] : (a == 1 ? EY[q] : EZ[q]);
-          r[a] = co[a] + e;
-          if (g.periodic[a]) {
-            if (r[a] < 0) r[a] += g.n[a];
-            if (r[a] >= g.n[a]) r[a] -= g.n[a];
-          } else if (r[a] < 0 || r[a] >= g.n[a]) {
-            in = false;
-          }
-        }
-        if (in) {
-          const long long ri = cell_index(g, c.b, r[0], r[1], r[2]);
-          if (!solid_at(ph, ri) && !is_inflow(g, r[0], r[1], r[2])) {
-            Af[at(q, ri)] = of[q];
-            Ag[at(q, ri)] = og[q];
-          }
-        }
-        // bounce-back receiver: this cell, when its pull of opp(q) hits a solid
-        if (!inflow && pull_general(g, ph, c, OPP[q]).bounce) {
-          Af[at(OPP[q], c.idx)] = of[q];
-          Ag[at(OPP[q], c.idx)] = og[q];
-        }
-        // readers whose pull of q is clamped onto this cell
-        if (ft >= 0 && q > 0) {
-          const size_t k = (size_t)ft * (Q - 1) + (q - 1);
-          if (ftgt[k] >= 0)
-            for (int m = 0; m < 7; ++m) {
-              const int ri = frd[k * 7 + m];
-              if (ri >= 0) {
-                Af[at(q, ri)] = of[q];
-                Ag[at(q, ri)] = og[q];
-              }
-            }
-        }
-      }
+      bad = collide_emit<Cd>(
+          ph, c, pg, pf, [&](int q, El v) { Ag[at(q, src_fast(g, c, fc, OPP[q]))] = v; },
+          [&](int q, El v) { Af[at(q, src_fast(g, c, fc, OPP[q]))] = v; });
     }
   }
   count_lanes(bad, counters, 0);

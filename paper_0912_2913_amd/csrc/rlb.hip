@@ -54,6 +54,8 @@ struct rlb_solver {
   int aa_phase;               // 0: swapped layout (S_t readable), 1: streamed layout
   void *d_fb;                 // face copies of the in-place layout
   FaceMap fm;
+  int *d_aalist;              // cells of the in-place general path
+  int n_aablk;
 };
 
 namespace {
@@ -242,11 +244,13 @@ rlb_status launch_steps(rlb_solver *h, int nsteps) {
   if (h->inplace) {
     El *A = (El *)h->pop[0];
     for (int s = 0; s < nsteps; ++s) {
-      if (h->aa_phase == 0)
-        hipLaunchKernelGGL((k_aa_pull<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream,
-                           h->g, h->ph, h->fm, A, (const El *)h->d_fb, (const int *)h->d_ftgt,
-                           (const int *)h->d_frd, in_eq, h->d_counters);
-      else
+      if (h->aa_phase == 0) {
+        // listed cells (general path) and the rest (fast path) in one launch
+        hipLaunchKernelGGL((k_aa_pull_all<ST, TC>), dim3(h->n_aablk + grid_blocks(h)), dim3(BLOCK),
+                           0, h->stream, h->g, h->ph, h->fm, h->n_aablk,
+                           (const int *)h->d_aalist, A, (const El *)h->d_fb,
+                           (const int *)h->d_ftgt, (const int *)h->d_frd, in_eq, h->d_counters);
+      } else
         hipLaunchKernelGGL((k_aa_local<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream,
                            h->g, h->ph, h->fm, A, (El *)h->d_fb, in_eq, h->d_counters);
       h->aa_phase = 1 - h->aa_phase;
@@ -329,6 +333,32 @@ rlb_status launch_fields_g(rlb_solver *h, const void *Sg, double *e, double *bet
 // Cells of the general reverse kernel, in index order, each instance padded to
 // whole workgroups (-1 entries), so that every workgroup's partial sums belong
 // to one instance and their reduction order is fixed.
+// Cells of the in-place general path (flagged by k_mark_aa), in index order,
+// padded to whole workgroups.
+rlb_status build_aa_list(rlb_solver *h) {
+  const size_t cells = (size_t)h->g.per * h->p.batch;
+  uint8_t *d_flag = nullptr;
+  RLB_HIP(hipMalloc(&d_flag, cells));
+  hipLaunchKernelGGL(k_mark_aa, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
+                     d_flag);
+  std::vector<uint8_t> flag(cells);
+  hipError_t e = hipMemcpyAsync(flag.data(), d_flag, cells, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(d_flag);
+  if (e != hipSuccess) return fail(RLB_EDEVICE, std::string("in-place list: ") + hipGetErrorString(e));
+  std::vector<int> list;
+  for (size_t i = 0; i < cells; ++i)
+    if (flag[i]) list.push_back((int)i);
+  if (!list.empty())
+    while (list.size() % (8 * BLOCK)) list.push_back(-1);  // whole XCD rounds of workgroups
+  h->n_aablk = (int)(list.size() / BLOCK);
+  if (h->n_aablk > 0) {
+    RLB_HIP(hipMalloc(&h->d_aalist, list.size() * sizeof(int)));
+    RLB_HIP(hipMemcpy(h->d_aalist, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
+  return RLB_OK;
+}
+
 // Face-reader table (once per solver): readers whose pulls clamp onto face cells.
 rlb_status build_faces_table(rlb_solver *h) {
   if (h->faces.count == 0 || h->d_ftgt) return RLB_OK;
@@ -508,6 +538,7 @@ void free_solver(rlb_solver *h) {
   if (h->d_dtau_cell) (void)hipFree(h->d_dtau_cell);
   if (h->d_bad) (void)hipFree(h->d_bad);
   if (h->d_fb) (void)hipFree(h->d_fb);
+  if (h->d_aalist) (void)hipFree(h->d_aalist);
   delete h;
 }
 
@@ -646,7 +677,7 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
     if (fm.nf > 0 &&
         (e = hipMalloc(&h->d_fb, (size_t)2 * Q * fm.nf * h->elem)) != hipSuccess)
       return cleanup_fail(e, "hipMalloc(face copies)");
-    if ((s = build_faces_table(h)) != RLB_OK) {
+    if ((s = build_faces_table(h)) != RLB_OK || (s = build_aa_list(h)) != RLB_OK) {
       free_solver(h);
       return s;
     }
