@@ -60,15 +60,17 @@ class GRun:
             self.final = sv.new_g()
             sv.advance_g(s0, self.final, tmp, self.T)
             return sv.fields_g(self.final)
+        # advance between two fixed buffers (the library replays one cached
+        # graph per buffer pair and segment length) and copy out checkpoints
         self.ckpt = [s0]
+        a, b = s0.clone(), sv.new_g()
         for k in range(self.K):
             n = min(self.S, self.T - k * self.S)
-            dst = sv.new_g()
-            sv.advance_g(self.ckpt[k], dst, tmp, max(n, 0))
+            sv.advance_g(a, b, tmp, max(n, 0))
             if k + 1 < self.K:
-                self.ckpt.append(dst)
-            else:
-                self.final = dst
+                self.ckpt.append(b.clone())
+            a, b = b, a
+        self.final = a
         return sv.fields_g(self.final)
 
     def backward(self, dLde: torch.Tensor, dLdb: torch.Tensor):

@@ -759,6 +759,12 @@ __global__ __launch_bounds__(BLOCK) void k_finish(const double *__restrict__ par
   }
 }
 
+// v[0..n) = 0 (a kernel, not a memset, so that it may sit in captured graphs).
+__global__ __launch_bounds__(BLOCK) void k_zero(double *__restrict__ v, long long n) {
+  const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) v[i] = 0.0;
+}
+
 // de_in[0] += sum_b inst[b][0]; dbeta_in[k] += sum_b inst[b][1 + k] (in order).
 __global__ void k_finish_inflow(const double *__restrict__ inst, int batch,
                                 double *__restrict__ de_in, double *__restrict__ dbeta_in) {

@@ -11,6 +11,11 @@
 #include "../../include/rlb.h"
 #include "kernels.hpp"
 
+// Loop entry points with at least this many steps replay a cached HIP graph
+// of their launches (kernels only) instead of launching step by step.
+constexpr int kGraphMin = 4;
+constexpr int kGraphSlots = 12;
+
 using namespace rlb;
 
 struct rlb_solver {
@@ -56,6 +61,16 @@ struct rlb_solver {
   FaceMap fm;
   int *d_aalist;              // cells of the in-place general path
   int n_aablk;
+  // Loops of launches replayed as HIP graphs (one per distinct call signature)
+  hipStream_t cap;            // private stream the loops are captured on
+  struct GraphEntry {
+    int kind;                 // 0 none, 1 advance, 2 trajectory, 3 sweep
+    const void *a, *b, *c;
+    int64_t stride;
+    int n;
+    hipGraphExec_t exec;
+  } graphs[kGraphSlots];
+  int graph_next;
 };
 
 namespace {
@@ -371,6 +386,54 @@ rlb_status build_faces_table(rlb_solver *h) {
   return RLB_OK;
 }
 
+void drop_graphs(rlb_solver *h) {
+  for (int i = 0; i < kGraphSlots; ++i)
+    if (h->graphs[i].kind) {
+      (void)hipGraphExecDestroy(h->graphs[i].exec);
+      h->graphs[i].kind = 0;
+    }
+}
+
+// Run `body` (which launches on h->stream) through a cached graph keyed by
+// (kind, a, b, c, stride, n): captured on a private stream the first time,
+// replayed on h->stream afterwards.  Kernel arguments (geometry, physics,
+// buffers) are fixed at capture; anything that changes them drops the cache.
+template <class F>
+rlb_status run_graph(rlb_solver *h, int kind, const void *a, const void *b, const void *c,
+                     int64_t stride, int n, F body) {
+  for (int i = 0; i < kGraphSlots; ++i) {
+    const auto &G = h->graphs[i];
+    if (G.kind == kind && G.a == a && G.b == b && G.c == c && G.stride == stride && G.n == n) {
+      RLB_HIP(hipGraphLaunch(G.exec, h->stream));
+      return RLB_OK;
+    }
+  }
+  if (!h->cap) RLB_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  hipStream_t user = h->stream;
+  RLB_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  h->stream = h->cap;
+  rlb_status st = body();
+  h->stream = user;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(h->cap, &graph);
+  if (st != RLB_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(RLB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess)
+    return fail(RLB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  auto &G = h->graphs[h->graph_next];
+  if (G.kind) (void)hipGraphExecDestroy(G.exec);
+  G = {kind, a, b, c, stride, n, exec};
+  h->graph_next = (h->graph_next + 1) % kGraphSlots;
+  RLB_HIP(hipGraphLaunch(exec, h->stream));
+  return RLB_OK;
+}
+
 rlb_status build_adjoint_list(rlb_solver *h) {
   const size_t cells = (size_t)h->g.per * h->p.batch;
   uint8_t *d_flag = nullptr;
@@ -459,6 +522,22 @@ rlb_status flush_adjoint(rlb_solver *h, double *dtau, double *dbeta_in, double *
   return RLB_OK;
 }
 
+// Start the pending reverse-step partials at zero (kernels only), so that
+// steps may always accumulate.
+rlb_status zero_reverse_partials(rlb_solver *h) {
+  const long long n1 = 5LL * h->g.nblk;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n1 + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, h->stream,
+                     h->d_part_rev, n1);
+  if (h->n_gblk > 0) {
+    const long long n2 = 5LL * h->n_gblk;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n2 + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                       h->stream, h->d_part2, n2);
+  }
+  h->rev_pending = true;
+  RLB_HIP(hipGetLastError());
+  return RLB_OK;
+}
+
 template <int ST, class TC>
 rlb_status launch_moments_adjoint(rlb_solver *h, const void *S, const double *dLde,
                                   const double *dLdb, void *lam) {
@@ -539,6 +618,9 @@ void free_solver(rlb_solver *h) {
   if (h->d_bad) (void)hipFree(h->d_bad);
   if (h->d_fb) (void)hipFree(h->d_fb);
   if (h->d_aalist) (void)hipFree(h->d_aalist);
+  for (int i = 0; i < kGraphSlots; ++i)
+    if (h->graphs[i].kind) (void)hipGraphExecDestroy(h->graphs[i].exec);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   delete h;
 }
 
@@ -803,20 +885,29 @@ rlb_status rlb_adjoint_sweep(rlb_solver *h, const void *g_seq, int64_t seq_strid
     return fail(RLB_EINVAL, "adjoint sweep arguments invalid");
   rlb_status s = prepare_adjoint(h);
   if (s != RLB_OK) return s;
-  void *cur = lam_a, *nxt = lam_b;
-  for (int j = n - 1; j >= 0; --j) {
-    const void *S = (const char *)g_seq + (size_t)j * (size_t)seq_stride;
-    auto launch = [&]() -> rlb_status {
-      RLB_DISPATCH(h, launch_adjoint, h, S, (const void *)cur, nxt);
-    };
-    s = launch();
+  auto body = [&]() -> rlb_status {
+    void *cur = lam_a, *nxt = lam_b;
+    for (int j = n - 1; j >= 0; --j) {
+      const void *S = (const char *)g_seq + (size_t)j * (size_t)seq_stride;
+      auto launch = [&]() -> rlb_status {
+        RLB_DISPATCH(h, launch_adjoint, h, S, (const void *)cur, nxt);
+      };
+      rlb_status st = launch();
+      if (st != RLB_OK) return st;
+      void *t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+    return RLB_OK;
+  };
+  *lam_result = n % 2 == 0 ? lam_a : lam_b;
+  if (n < kGraphMin) return body();
+  // every captured step accumulates onto the pending partials: start them at zero
+  if (!h->rev_pending) {
+    s = zero_reverse_partials(h);
     if (s != RLB_OK) return s;
-    void *t = cur;
-    cur = nxt;
-    nxt = t;
   }
-  *lam_result = cur;
-  return RLB_OK;
+  return run_graph(h, 3, g_seq, lam_a, lam_b, seq_stride, n, body);
 }
 
 rlb_status rlb_adjoint_flush(rlb_solver *h, double *dL_dtau, double *dL_dbeta_in,
@@ -838,15 +929,19 @@ rlb_status rlb_advance_g(rlb_solver *h, const void *g_src, void *g_dst, void *g_
                            hipMemcpyDeviceToDevice, h->stream));
     return RLB_OK;
   }
-  const void *cur = g_src;
-  for (int i = 0; i < n; ++i) {
-    void *next = ((n - 1 - i) % 2 == 0) ? g_dst : g_tmp;  // the last step lands in g_dst
-    auto launch = [&]() -> rlb_status { RLB_DISPATCH(h, launch_step_g, h, cur, next); };
-    rlb_status s = launch();
-    if (s != RLB_OK) return s;
-    cur = next;
-  }
-  return RLB_OK;
+  auto body = [&]() -> rlb_status {
+    const void *cur = g_src;
+    for (int i = 0; i < n; ++i) {
+      void *next = ((n - 1 - i) % 2 == 0) ? g_dst : g_tmp;  // the last step lands in g_dst
+      auto launch = [&]() -> rlb_status { RLB_DISPATCH(h, launch_step_g, h, cur, next); };
+      rlb_status s = launch();
+      if (s != RLB_OK) return s;
+      cur = next;
+    }
+    return RLB_OK;
+  };
+  if (n < kGraphMin) return body();
+  return run_graph(h, 1, g_src, g_dst, g_tmp, 0, n, body);
 }
 
 rlb_status rlb_trajectory_g(rlb_solver *h, void *g_seq, int64_t seq_stride, int32_t n) {
@@ -856,14 +951,18 @@ rlb_status rlb_trajectory_g(rlb_solver *h, void *g_seq, int64_t seq_stride, int3
     return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   const int64_t need = (int64_t)Q * h->g.qs * (int64_t)h->elem;
   if (n < 1 || !g_seq || seq_stride < need) return fail(RLB_EINVAL, "trajectory arguments invalid");
-  for (int j = 1; j < n; ++j) {
-    const void *src = (const char *)g_seq + (size_t)(j - 1) * (size_t)seq_stride;
-    void *dst = (char *)g_seq + (size_t)j * (size_t)seq_stride;
-    auto launch = [&]() -> rlb_status { RLB_DISPATCH(h, launch_step_g, h, src, dst); };
-    rlb_status s = launch();
-    if (s != RLB_OK) return s;
-  }
-  return RLB_OK;
+  auto body = [&]() -> rlb_status {
+    for (int j = 1; j < n; ++j) {
+      const void *src = (const char *)g_seq + (size_t)(j - 1) * (size_t)seq_stride;
+      void *dst = (char *)g_seq + (size_t)j * (size_t)seq_stride;
+      auto launch = [&]() -> rlb_status { RLB_DISPATCH(h, launch_step_g, h, src, dst); };
+      rlb_status s = launch();
+      if (s != RLB_OK) return s;
+    }
+    return RLB_OK;
+  };
+  if (n - 1 < kGraphMin) return body();
+  return run_graph(h, 2, g_seq, nullptr, nullptr, seq_stride, n, body);
 }
 
 rlb_status rlb_moments_adjoint(rlb_solver *h, const void *g_state_T, const double *dL_de,
@@ -892,6 +991,8 @@ rlb_status rlb_init_adjoint(rlb_solver *h, const double *e0, const double *beta0
 
 rlb_status rlb_set_tau_field(rlb_solver *h, const double *tau_cell) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  RLB_HIP(hipStreamSynchronize(h->stream));
+  drop_graphs(h);  // captured kernels hold the old relaxation arguments
   const long long cells = (long long)h->g.batch * h->g.per;
   if (!tau_cell) {
     RLB_HIP(hipStreamSynchronize(h->stream));
@@ -941,6 +1042,10 @@ rlb_status rlb_hold_eta_over_s(rlb_solver *h, double eta_over_s, double d_G) {
     return fail(RLB_EINVAL, "transport quantities and the eta/s rule are defined for e = 3P (kappa = 1/3)");
   if (h->inplace && eta_over_s > 0.0)
     return fail(RLB_EINVAL, "holding eta/s is built for the two-buffer layout (inplace = 0)");
+  if (eta_over_s != h->ph.eta_s || d_G != h->ph.d_G) {
+    RLB_HIP(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+  }
   h->ph.eta_s = eta_over_s;
   h->ph.d_G = d_G;
   return RLB_OK;

@@ -338,3 +338,56 @@ def test_loop_entry_points_reject_bad_arguments():
     with pytest.raises(RLBError):
         sv.adjoint_sweep(seq, 2, la, la)
     sv.close()
+
+
+def test_graph_replays_match_step_by_step_launches():
+    """Loop entry points of 4 or more steps replay a cached graph: every replay,
+    with other work and synchronisations in between, matches the step-by-step
+    result bitwise (advance, trajectory, sweep; the sweep's partials too)."""
+    from paper_0912_2913_amd.solver import Solver
+
+    s = setups()["inflow_outflow_obstacle"]
+    sv = Solver(s)
+    g0 = upload_g(sv, _state_after(s, 2))
+    ref = [g0.clone()]
+    for _ in range(6):
+        nxt = sv.new_g().zero_()
+        sv.step_g(ref[-1], nxt)
+        ref.append(nxt)
+    fl = torch.as_tensor(s.solid == 0, device=sv.device)
+    dst, tmp = sv.new_g(), sv.new_g()
+    seq = sv.new_g_seq(6)
+    rng = np.random.default_rng(13)
+    lam_T = upload_lam(sv, rng.standard_normal((19, s.cells)))
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device=sv.device)
+    # the step-by-step sweep (single rlb_adjoint_step calls) as the reference
+    seq[0].copy_(g0)
+    sv.trajectory_g(seq, 3)  # < 4 steps: launched step by step
+    seq_ref = seq.clone()
+    for j in range(3, 6):
+        sv.step_g(seq_ref[j - 1], seq_ref[j])
+    a, b = lam_T.clone(), sv.new_lam()
+    g_ref = (z(s.batch), z(3), z(1))
+    for j in range(5, -1, -1):
+        sv.adjoint_step(seq_ref[j], a, b, *(g_ref if j == 0 else (None, None, None)))
+        a, b = b, a
+    lam_ref = sv.unpack(a).cpu()
+    for rep in range(3):
+        dst.fill_(float(rep))
+        sv.advance_g(g0, dst, tmp, 6)
+        assert torch.equal(bits(sv.unpack(dst)[:, fl]), bits(sv.unpack(ref[6])[:, fl])), rep
+        seq.fill_(-1.0)
+        seq[0].copy_(g0)
+        sv.trajectory_g(seq, 6)
+        for j in range(6):
+            assert torch.equal(bits(sv.unpack(seq[j])[:, fl]), bits(sv.unpack(seq_ref[j])[:, fl])), (rep, j)
+        torch.cuda.synchronize()
+        _ = (dst * 2).sum().item()  # unrelated eager work between replays
+        la, lb = lam_T.clone(), sv.new_lam().fill_(float("nan"))
+        res = sv.adjoint_sweep(seq, 6, la, lb)
+        g_sw = (z(s.batch), z(3), z(1))
+        sv.adjoint_flush(*g_sw)
+        assert torch.equal(sv.unpack(res).cpu(), lam_ref), rep
+        for x, y in zip(g_sw, g_ref):
+            assert torch.equal(x, y), rep
+    sv.close()
