@@ -903,17 +903,17 @@ __device__ __forceinline__ bool covered(const Geom &g, const Phys &ph, const Cel
   return false;
 }
 
-// Which reverse-step kernel handles a cell: the streaming kernel takes cells
+// Which path of the reverse step handles a cell: the streaming path takes cells
 // whose 19 sources and 19 targets are all plain (possibly wrapped) neighbours;
 // every other cell (solid, inflow, next to a solid, on an outflow face or next
-// to an inflow plane) goes to the general kernel, through a precomputed list.
+// to an inflow plane) goes to the general path, through a precomputed list.
 __device__ __forceinline__ bool adjoint_plain(const Geom &g, const Phys &ph, const Cell &c) {
   const uint8_t cls = ph.cls ? ph.cls[c.idx] : (uint8_t)0;
   return !(cls & (CLS_SOLID | CLS_NEAR)) && !is_inflow(g, c.x, c.y, c.z) &&
          in_fast(c, g.alo, g.ahi);
 }
 
-// Cell of a linear index (general kernel).
+// Cell of a linear index (general paths).
 __device__ __forceinline__ Cell cell_at(const Geom &g, long long idx) {
   Cell c;
   c.idx = idx;
@@ -971,42 +971,30 @@ __device__ __forceinline__ double adjoint_mu(const LocalAdjoint &a, double lam, 
   return mu;
 }
 
-// One reverse step of the g population (see rlb_adjoint_step), streaming part:
-// cells for which adjoint_plain() holds.  Each pulls pre from S_t, reads
-// lambda_{t+1}(x) and writes mu_q to lambda_t at the source of its pull q;
-// those targets cover every entry of lambda_t that no general cell writes.
-// part[L][5] = (dtau, 0, 0, 0, 0) partials of this workgroup, added to the
-// previous step's when accum is set (one reverse sweep accumulates per
-// workgroup in step order, then is reduced once).
-template <int ST, class TC>
-__global__ __launch_bounds__(BLOCK) void k_adjoint(
-    const Geom g, const Phys ph, const typename Codec<ST, TC>::elem *__restrict__ S,
-    const LamT *__restrict__ lam_next, LamT *__restrict__ lam_out, double *__restrict__ part,
-    int accum) {
-  using Cd = Codec<ST, TC>;
-  const Cell c = decode_cell(g);
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (c.active && adjoint_plain(g, ph, c)) {
-    double pre[Q], lam[Q];
-    const FaceCorr fc = face_corr(g, c);
+// Streaming part of one reverse step of the g population (see
+// rlb_adjoint_step), for a cell where adjoint_plain() holds: pulls pre from
+// S_t, reads lambda_{t+1}(x) and writes mu_q to lambda_t at the source of its
+// pull q; those targets cover every entry of lambda_t that no listed cell
+// writes.  Returns lambda . d post / d tau.
+template <class Cd>
+__device__ __forceinline__ double adjoint_stream_cell(const Geom &g, const Phys &ph, const Cell &c,
+                                                      const typename Cd::elem *__restrict__ S,
+                                                      const LamT *__restrict__ lam_next,
+                                                      LamT *__restrict__ lam_out) {
+  double pre[Q], lam[Q];
+  const FaceCorr fc = face_corr(g, c);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) pre[q] = (double)Cd::dec(S[at(q, src_fast(g, c, fc, q))]);
+  for (int q = 0; q < Q; ++q) pre[q] = (double)Cd::dec(S[at(q, src_fast(g, c, fc, q))]);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, c.idx)];
-    const LocalAdjoint a = adjoint_local(ph, omega_of(ph, c.b, c.idx), pre, lam);
+  for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, c.idx)];
+  const LocalAdjoint a = adjoint_local(ph, omega_of(ph, c.b, c.idx), pre, lam);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) lam_out[at(q, src_fast(g, c, fc, q))] = adjoint_mu(a, lam[q], q);
-    acc[0] = a.dtau;
-    if (ph.dtau_cell) ph.dtau_cell[c.idx] += a.dtau;
-  }
-  double out[5];
-  block_sum<5>(acc, out);
-  if (threadIdx.x == 0)
-    for (int k2 = 0; k2 < 5; ++k2)
-      part[(size_t)c.L * 5 + k2] = (accum ? part[(size_t)c.L * 5 + k2] : 0.0) + out[k2];
+  for (int q = 0; q < Q; ++q) lam_out[at(q, src_fast(g, c, fc, q))] = adjoint_mu(a, lam[q], q);
+  if (ph.dtau_cell) ph.dtau_cell[c.idx] += a.dtau;
+  return a.dtau;
 }
 
-// Per listed cell of the general reverse kernel, precomputed once: the 19
+// Per listed cell of the general reverse path, precomputed once: the 19
 // pull sources (source cell and direction, bounce-back and clamp flags) and
 // the mask of its own lambda_t entries that no update writes.  Layout [Q][n]
 // so that consecutive list entries read consecutive words.
@@ -1047,75 +1035,105 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_table(const Geom g, const Phy
   }
 }
 
-// General part of the reverse step, over the listed cells (list[i] = linear
-// cell index, -1 = padding; each instance's cells fill whole workgroups).
-// Zeroes the entries of lambda_t that no update writes, routes inflow cells'
-// lambda_{t+1} into the inflow gradient, and scatters through the general
-// pull read from T (bounce-back to the cell's own opposite entry; clamped
-// pulls into `scratch`, indexed by the reading cell, for k_adjoint_faces).
-// part[blk][5] = (dtau, de_in, dbeta_in[3]) partials of this workgroup
-// (accumulated across steps like k_adjoint's).
-template <int ST, class TC>
-__global__ __launch_bounds__(BLOCK) void k_adjoint_general(
-    const Geom g, const Phys ph, const int *__restrict__ list, const GenTable T,
-    const typename Codec<ST, TC>::elem *__restrict__ S, const LamT *__restrict__ lam_next,
-    LamT *__restrict__ lam_out, LamT *__restrict__ scratch, double *__restrict__ part,
-    const InflowState in, int accum) {
-  using Cd = Codec<ST, TC>;
-  const int i = (int)(blockIdx.x * BLOCK + threadIdx.x);
-  const int li = list[i];
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (li >= 0) {
-    const unsigned inf = T.info[i];
-    const bool solid = inf & 1u;
-    const bool inflow = inf & 2u;
-    const unsigned unc = inf >> 8;
-    for (int p = 0; p < Q; ++p)
-      if ((unc >> p) & 1u) lam_out[at(p, li)] = 0.0;
-    if (inflow) {
-      double lam[Q];
+// General part of the reverse step, for listed cell li = list[i] (see
+// GenTable): zeroes the entries of lambda_t that no update writes, routes an
+// inflow cell's lambda_{t+1} into the inflow gradient (acc[1..4] = de_in,
+// dbeta_in), and scatters through the general pull read from T (bounce-back to
+// the cell's own opposite entry; clamped pulls into `scratch`, indexed by the
+// reading cell, for k_adjoint_faces); acc[0] = lambda . d post / d tau.
+template <class Cd>
+__device__ __forceinline__ void adjoint_general_cell(
+    const Geom &g, const Phys &ph, int li, int i, const GenTable &T,
+    const typename Cd::elem *__restrict__ S, const LamT *__restrict__ lam_next,
+    LamT *__restrict__ lam_out, LamT *__restrict__ scratch, const InflowState &in,
+    double (&acc)[5]) {
+  const unsigned inf = T.info[i];
+  const bool solid = inf & 1u;
+  const bool inflow = inf & 2u;
+  const unsigned unc = inf >> 8;
+  for (int p = 0; p < Q; ++p)
+    if ((unc >> p) & 1u) lam_out[at(p, li)] = 0.0;
+  if (inflow) {
+    double lam[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, li)];
-      const double g2 = 1.0 / (1.0 - (in.bx * in.bx + in.by * in.by + in.bz * in.bz));
-      const double W = (4.0 / 3.0) * in.e * g2;
-      const EqCoef<double> k = eq_coef<double>(ph, 0.0, in.e, W, in.bx, in.by, in.bz);
-      const LamEq L = lam_eq(lam_sums(lam, k), ph, W, in.bx, in.by, in.bz);
-      double gr[4];
-      eq_param_grad(L, in.e, in.bx, in.by, in.bz, gr);
-      for (int k2 = 0; k2 < 4; ++k2) acc[1 + k2] = gr[k2];
-    } else if (!solid) {
-      double pre[Q], lam[Q];
+    for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, li)];
+    const double g2 = 1.0 / (1.0 - (in.bx * in.bx + in.by * in.by + in.bz * in.bz));
+    const double W = (4.0 / 3.0) * in.e * g2;
+    const EqCoef<double> k = eq_coef<double>(ph, 0.0, in.e, W, in.bx, in.by, in.bz);
+    const LamEq L = lam_eq(lam_sums(lam, k), ph, W, in.bx, in.by, in.bz);
+    double gr[4];
+    eq_param_grad(L, in.e, in.bx, in.by, in.bz, gr);
+    for (int k2 = 0; k2 < 4; ++k2) acc[1 + k2] = gr[k2];
+  } else if (!solid) {
+    double pre[Q], lam[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q)
-        pre[q] = (double)Cd::dec(S[at(T.srcq[(size_t)q * T.n + i] & 31, T.src[(size_t)q * T.n + i])]);
+    for (int q = 0; q < Q; ++q)
+      pre[q] = (double)Cd::dec(S[at(T.srcq[(size_t)q * T.n + i] & 31, T.src[(size_t)q * T.n + i])]);
 #pragma unroll
-      for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, li)];
-      const int b = li / g.per;
-      const LocalAdjoint a = adjoint_local(ph, omega_of(ph, b, li), pre, lam);
+    for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, li)];
+    const int b = li / g.per;
+    const LocalAdjoint a = adjoint_local(ph, omega_of(ph, b, li), pre, lam);
+    // Read the table again for the scatter rather than keep the 38 entries
+    // live across the local update (the empty asm hides that the addresses
+    // are the gather's): that keeps this path within the streaming path's
+    // register budget, so that sharing one kernel costs no occupancy.
+    int j = i;
+    asm volatile("" : "+v"(j));
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const double mu = adjoint_mu(a, lam[q], q);
-        const unsigned fl = T.srcq[(size_t)q * T.n + i];
-        if (fl & 32u)
-          lam_out[at(OPP[q], li)] = mu;
-        else if (fl & 64u)
-          scratch[at(q, li)] = mu;
-        else
-          lam_out[at(q, T.src[(size_t)q * T.n + i])] = mu;
-      }
-      acc[0] = a.dtau;
-      if (ph.dtau_cell) ph.dtau_cell[li] += a.dtau;
+    for (int q = 0; q < Q; ++q) {
+      const double mu = adjoint_mu(a, lam[q], q);
+      const unsigned fl = T.srcq[(size_t)q * T.n + j];
+      if (fl & 32u)
+        lam_out[at(OPP[q], li)] = mu;
+      else if (fl & 64u)
+        scratch[at(q, li)] = mu;
+      else
+        lam_out[at(q, T.src[(size_t)q * T.n + j])] = mu;
     }
+    acc[0] = a.dtau;
+    if (ph.dtau_cell) ph.dtau_cell[li] += a.dtau;
+  }
+}
+
+// One reverse step of the g population (see rlb_adjoint_step) in one launch.
+// The first nlist workgroups (a multiple of 8, so that the others keep their
+// XCD placement) take the listed cells, list[blk * BLOCK + lane] for blk <
+// ngen (-1 = padding; each instance's cells fill whole workgroups), on the
+// general path; the others take the cells where adjoint_plain() holds.  The
+// two sets write disjoint entries of lambda_t, and the listed cells'
+// latency-bound work overlaps the streaming of the rest.  Partials, added to
+// the previous step's when accum is set (a reverse sweep accumulates per
+// workgroup in step order, then reduces once): part[L][5] = (dtau, 0, 0, 0, 0)
+// of streaming workgroup L, part2[blk][5] = (dtau, de_in, dbeta_in[3]) of
+// listed workgroup blk.
+template <int ST, class TC>
+__global__ __launch_bounds__(BLOCK) void k_adjoint(
+    const Geom g, const Phys ph, int nlist, int ngen, const int *__restrict__ list,
+    const GenTable T, const typename Codec<ST, TC>::elem *__restrict__ S,
+    const LamT *__restrict__ lam_next, LamT *__restrict__ lam_out, LamT *__restrict__ scratch,
+    double *__restrict__ part, double *__restrict__ part2, const InflowState in, int accum) {
+  using Cd = Codec<ST, TC>;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double *dst;
+  if ((int)blockIdx.x < nlist) {
+    if ((int)blockIdx.x >= ngen) return;
+    const int i = (int)(blockIdx.x * BLOCK + threadIdx.x);
+    const int li = list[i];
+    if (li >= 0) adjoint_general_cell<Cd>(g, ph, li, i, T, S, lam_next, lam_out, scratch, in, acc);
+    dst = part2 + (size_t)blockIdx.x * 5;
+  } else {
+    const Cell c = decode_cell(g, (int)blockIdx.x - nlist);
+    if (c.active && adjoint_plain(g, ph, c))
+      acc[0] = adjoint_stream_cell<Cd>(g, ph, c, S, lam_next, lam_out);
+    dst = part + (size_t)c.L * 5;
   }
   double out[5];
   block_sum<5>(acc, out);
   if (threadIdx.x == 0)
-    for (int k2 = 0; k2 < 5; ++k2)
-      part[(size_t)blockIdx.x * 5 + k2] =
-          (accum ? part[(size_t)blockIdx.x * 5 + k2] : 0.0) + out[k2];
+    for (int k2 = 0; k2 < 5; ++k2) dst[k2] = (accum ? dst[k2] : 0.0) + out[k2];
 }
 
-// flag[cell] = 1 for the cells of the general reverse kernel (host builds the list).
+// flag[cell] = 1 for the cells of the general reverse path (host builds the list).
 __global__ __launch_bounds__(BLOCK) void k_mark_general(const Geom g, const Phys ph,
                                                         uint8_t *__restrict__ flag) {
   const Cell c = decode_cell(g);

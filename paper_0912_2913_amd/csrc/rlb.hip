@@ -345,7 +345,7 @@ rlb_status launch_fields_g(rlb_solver *h, const void *Sg, double *e, double *bet
   return RLB_OK;
 }
 
-// Cells of the general reverse kernel, in index order, each instance padded to
+// Cells of the general reverse path, in index order, each instance padded to
 // whole workgroups (-1 entries), so that every workgroup's partial sums belong
 // to one instance and their reduction order is fixed.
 // Cells of the in-place general path (flagged by k_mark_aa), in index order,
@@ -487,16 +487,13 @@ template <int ST, class TC>
 rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_next, void *lam_out) {
   using El = typename Codec<ST, TC>::elem;
   const int accum = h->rev_pending ? 1 : 0;
-  hipLaunchKernelGGL((k_adjoint<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
-                     h->ph, (const El *)S, (const LamT *)lam_next, (LamT *)lam_out, h->d_part_rev,
-                     accum);
-  if (h->n_gblk > 0) {
-    const GenTable T{h->d_gsrc, h->d_gsrcq, h->d_ginfo, h->glist_total};
-    hipLaunchKernelGGL((k_adjoint_general<ST, TC>), dim3(h->n_gblk), dim3(BLOCK), 0, h->stream,
-                       h->g, h->ph, (const int *)h->d_glist, T, (const El *)S,
-                       (const LamT *)lam_next, (LamT *)lam_out, (LamT *)h->d_scratch, h->d_part2,
-                       h->in, accum);
-  }
+  // Listed workgroups first, padded to a multiple of the 8 XCDs.
+  const int nlist = (h->n_gblk + 7) / 8 * 8;
+  const GenTable T{h->d_gsrc, h->d_gsrcq, h->d_ginfo, h->glist_total};
+  hipLaunchKernelGGL((k_adjoint<ST, TC>), dim3(nlist + grid_blocks(h)), dim3(BLOCK), 0, h->stream,
+                     h->g, h->ph, nlist, h->n_gblk, (const int *)h->d_glist, T, (const El *)S,
+                     (const LamT *)lam_next, (LamT *)lam_out, (LamT *)h->d_scratch,
+                     h->d_part_rev, h->d_part2, h->in, accum);
   if (h->faces.count > 0) {
     const long long npairs = h->faces.start[h->faces.count] * (Q - 1);
     hipLaunchKernelGGL(k_adjoint_faces<LamT>, dim3((unsigned)((npairs + BLOCK - 1) / BLOCK)),
