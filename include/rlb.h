@@ -6,9 +6,10 @@
  * (arXiv:0912.2913): a number population f_i and an energy-momentum
  * population g_i per cell and velocity, relaxed by one BGK time tau
  * (eqs. lbe1, lbe2) toward the ultra-relativistic equilibria
- * (eqs. equil1s, equil2as, equil2bs), with (n, e, beta) recovered from the
- * macroscopic constraints n gamma = sum f_i, (e+P) gamma^2 - P = sum g_i,
- * (e+P) gamma^2 beta = sum g_i c_i closed by e = 3P.
+ * (eqs. equil1s, equil2as, equil2bs; for P = kappa e with kappa != 1/3 the
+ * general ones, eqs. equil1, equil2a, equil2b), with (n, e, beta) recovered
+ * from the macroscopic constraints n gamma = sum f_i, (e+P) gamma^2 - P =
+ * sum g_i, (e+P) gamma^2 beta = sum g_i c_i closed by the equation of state.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -91,7 +92,7 @@ typedef enum {
 typedef enum { RLB_COLLIDE_AUTO = 0, RLB_COLLIDE_F32 = 1, RLB_COLLIDE_F64 = 2 } rlb_collide;
 
 /* Problem statement (shock-tube and obstacle sections of the paper: domain,
- * lattice speed c_l, fixed obstacle, inflow state; e = 3P is built in). */
+ * lattice speed c_l, fixed obstacle, inflow state; equation of state). */
 typedef struct {
   int32_t nx, ny, nz, batch; /* extents (>= 1); batch independent lattices       */
   double c_l;                /* lattice speed in units of c (> 0)                */
@@ -177,7 +178,8 @@ rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double
 rlb_status rlb_fields_g(rlb_solver *h, const void *g_state, double *e, double *beta);
 
 /* Counters of the steps run since the last call (synchronises): counts[0] =
- * unphysical g updates (4E^2 - 3|M|^2 <= 0, e <= 0, |beta| >= 1 or NaN);
+ * unphysical g updates (no real root of the inversion, 4E^2 - 3|M|^2 <= 0
+ * for e = 3P; e <= 0, |beta| >= 1 or NaN);
  * counts[1] = f updates whose equilibrium had a non-positive component
  * (some c_i.beta <= -c_l^2/3, the paper's positivity bound).  Resets both.
  * Returns RLB_EUNPHYSICAL when counts[0] > 0. */
@@ -186,7 +188,8 @@ rlb_status rlb_counters(rlb_solver *h, int64_t counts[2]);
 /* One reverse step of the g population (the transpose of the linearised
  * update of eq. lbe2 with its streaming and boundary rules):
  *   lam_out = (d S_{t+1} / d S_t)^T lam_next,
- * where S_{t+1} = step(S_t) with S_t = g_state_t (a g block).  lam_next and
+ * where S_{t+1} = step(S_t) with S_t = g_state_t (a g block), for the
+ * solver's equation of state (any kappa).  lam_next and
  * lam_out are device double blocks (brick layout) for every storage, distinct;
  * lam_out is overwritten, lam_next is not modified.  The step's parameter
  * contributions,
@@ -256,7 +259,8 @@ rlb_status rlb_set_tau_field(rlb_solver *h, const double *tau_cell);
  * depends on n, i.e. on f, so rlb_step_g, rlb_advance_g, rlb_trajectory_g,
  * rlb_adjoint_step and rlb_adjoint_sweep return RLB_EINVAL while it is on.
  * eta_over_s = 0 turns it off.  RLB_EINVAL for eta_over_s < 0, d_G <= 0 or
- * non-finite values.  Host-only (no device work). */
+ * non-finite values, and for eta_over_s > 0 with kappa != 1/3 (the rule and
+ * T = e/(3n) are those of e = 3P matter).  Host-only (no device work). */
 rlb_status rlb_hold_eta_over_s(rlb_solver *h, double eta_over_s, double d_G);
 
 /* Transport quantities of the current state per cell (device double
@@ -265,7 +269,8 @@ rlb_status rlb_hold_eta_over_s(rlb_solver *h, double eta_over_s, double d_G);
  * rule's tau at these fields): T = e/(3n); s = 4n - n ln(n/n_eq) with
  * n_eq = d_G T^3/pi^2; eta = (4/9) gamma^2 e c_l (tau - 1/2); eta_over_s.
  * d_G > 0 (16 for gluons); while eta/s is held it must equal the d_G given
- * there.  Asynchronous. */
+ * there.  RLB_EINVAL for kappa != 1/3 (these are e = 3P relations).
+ * Asynchronous. */
 rlb_status rlb_transport(rlb_solver *h, double d_G, double *T, double *s, double *eta,
                          double *eta_over_s);
 

@@ -780,16 +780,21 @@ __global__ void k_finish_inflow(const double *__restrict__ inst, int batch,
 // ---------------------------------------------------------------------------
 // Reverse mode.
 //
-// With g^eq_i = w_i [A_i e + W P_i(beta)] (A_i = 1/c_l^2, P_i = 3b_i +
-// (9/2) b_i^2 - s for i > 0; A_0 = -(2 + c_l^2)/c_l^2, P_0 = 3 - s) the
-// contraction of lambda with the equilibrium's partials is
-//   Le = sum l_i w_i A_i,  LW = sum l_i w_i P_i,
+// Eqs. (equil2a)/(equil2b) with P = kappa e and W = (e + P) gamma^2 read
+// g^eq_i = w_i [A_i e + W P_i(beta)] with A_i = a = 3 kappa / c_l^2,
+// P_i = 3b_i + (9/2) b_i^2 - s for i > 0 and A_0 = -a (2 + c_l^2),
+// P_0 = 3 - s (e = 3P: a = 1/c_l^2).  The contraction of lambda with the
+// equilibrium's partials is
+//   Le = sum l_i w_i A_i = a (sum l_i w_i - (3 + c_l^2) l_0 w_0),
+//   LW = sum l_i w_i P_i,
 //   Lb_a = (W / c_l) [sum_{i>0} l_i w_i e_ia (3 + 9 b_i) - 3 (beta_a / c_l) sum l_i w_i],
-// and the inversion's partials (D^2 = 4E^2 - 3|M|^2, e = D - E,
-// W = (2E + D)/3, beta = M/W) carry it to the moments:
+// and the inversion's partials (D^2 = A E^2 - B|M|^2, e = (D - F E) G,
+// W = (C E + D) H, beta = M/W; see invert) carry it to the moments:
 //   K = LW - Lb.beta / W,
-//   dL/dE = Le (4E/D - 1) + K (2 + 4E/D) / 3,
-//   dL/dM_a = -(M_a / D)(3 Le + K) + Lb_a / W.
+//   dL/dE = Le (A E/D - F) G + K (C + A E/D) H,
+//   dL/dM_a = -(M_a / D) B (G Le + H K) + Lb_a / W,
+// which for e = 3P is Le (4E/D - 1) + K (2 + 4E/D) / 3 and
+// -(M_a / D)(3 Le + K) + Lb_a / W.
 template <class T>
 struct LamSums {
   T Slw, SW, Vx, Vy, Vz, lw0;
@@ -833,7 +838,7 @@ __device__ __forceinline__ LamEq lam_eq(const LamSums<T> &s, const Phys &ph, dou
                                         double by, double bz) {
   LamEq r;
   const double Slw = (double)s.Slw;
-  r.Le = Slw * ph.inv_c2 - (double)s.lw0 * (3.0 + ph.c * ph.c) * ph.inv_c2;
+  r.Le = Slw * ph.ad_c - (double)s.lw0 * (3.0 + ph.c * ph.c) * ph.ad_c;
   r.LW = (double)s.SW;
   const double f = W * ph.inv_c;
   r.Lbx = f * ((double)s.Vx - 3.0 * bx * ph.inv_c * Slw);
@@ -847,26 +852,26 @@ struct GradEM {
   double gE, gx, gy, gz;
 };
 
-__device__ __forceinline__ GradEM chain_moments(const Inv &iv, double Le, double LW, double Lbx,
-                                                double Lby, double Lbz) {
+__device__ __forceinline__ GradEM chain_moments(const Phys &ph, const Inv &iv, double Le, double LW,
+                                                double Lbx, double Lby, double Lbz) {
   GradEM r;
   const double iW = 1.0 / iv.W, iD = 1.0 / iv.D;
   const double K = LW - (Lbx * iv.bx + Lby * iv.by + Lbz * iv.bz) * iW;
-  const double rr = 4.0 * iv.E * iD;
-  r.gE = Le * (rr - 1.0) + K * (2.0 + rr) * (1.0 / 3.0);
-  const double h = (3.0 * Le + K) * iD;
+  const double rr = ph.eos_A * iv.E * iD;
+  r.gE = Le * (rr - ph.eos_F) * ph.eos_G + K * (ph.eos_C + rr) * ph.eos_H;
+  const double h = (ph.eos_B * ph.eos_G * Le + ph.eos_B * ph.eos_H * K) * iD;
   r.gx = -iv.Mx * h + Lbx * iW;
   r.gy = -iv.My * h + Lby * iW;
   r.gz = -iv.Mz * h + Lbz * iW;
   return r;
 }
 
-// d/d(e, beta) of w_i [A_i e + W P_i] at W = (4/3) e gamma^2, contracted with lambda.
-__device__ __forceinline__ void eq_param_grad(const LamEq &L, double e, double bx, double by,
-                                              double bz, double out[4]) {
+// d/d(e, beta) of w_i [A_i e + W P_i] at W = (1 + kappa) e gamma^2, contracted with lambda.
+__device__ __forceinline__ void eq_param_grad(const Phys &ph, const LamEq &L, double e, double bx,
+                                              double by, double bz, double out[4]) {
   const double g2 = 1.0 / (1.0 - (bx * bx + by * by + bz * bz));
-  const double W = (4.0 / 3.0) * e * g2;
-  out[0] = L.Le + (4.0 / 3.0) * g2 * L.LW;
+  const double W = ph.wfac * e * g2;
+  out[0] = L.Le + ph.wfac * g2 * L.LW;
   const double t = 2.0 * W * g2 * L.LW;
   out[1] = L.Lbx + t * bx;
   out[2] = L.Lby + t * by;
@@ -948,7 +953,7 @@ __device__ __forceinline__ LocalAdjoint adjoint_local(const Phys &ph, double om,
   const EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
   T dt;
   const LamEq L = lam_eq(lam_sums(lam, k, pre, &dt), ph, iv.W, iv.bx, iv.by, iv.bz);
-  const GradEM gm = chain_moments(iv, L.Le, L.LW, L.Lbx, L.Lby, L.Lbz);
+  const GradEM gm = chain_moments(ph, iv, L.Le, L.LW, L.Lbx, L.Lby, L.Lbz);
   LocalAdjoint r;
   r.om1 = 1.0 - om;
   r.aE = om * gm.gE;
@@ -1058,11 +1063,11 @@ __device__ __forceinline__ void adjoint_general_cell(
 #pragma unroll
     for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, li)];
     const double g2 = 1.0 / (1.0 - (in.bx * in.bx + in.by * in.by + in.bz * in.bz));
-    const double W = (4.0 / 3.0) * in.e * g2;
+    const double W = ph.wfac * in.e * g2;
     const EqCoef<double> k = eq_coef<double>(ph, 0.0, in.e, W, in.bx, in.by, in.bz);
     const LamEq L = lam_eq(lam_sums(lam, k), ph, W, in.bx, in.by, in.bz);
     double gr[4];
-    eq_param_grad(L, in.e, in.bx, in.by, in.bz, gr);
+    eq_param_grad(ph, L, in.e, in.bx, in.by, in.bz, gr);
     for (int k2 = 0; k2 < 4; ++k2) acc[1 + k2] = gr[k2];
   } else if (!solid) {
     double pre[Q], lam[Q];
@@ -1274,7 +1279,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments_adjoint(
   }
   mirror_sums(gv, sx, sy, sz);
   const Inv iv = invert(ph, ph.e_ref + sE, ph.c * sx, ph.c * sy, ph.c * sz);
-  const GradEM gm = chain_moments(iv, dLde[c.idx], 0.0, dLdb[c.idx], dLdb[cells + c.idx],
+  const GradEM gm = chain_moments(ph, iv, dLde[c.idx], 0.0, dLdb[c.idx], dLdb[cells + c.idx],
                                   dLdb[2 * cells + c.idx]);
   const double ax = ph.c * gm.gx, ay = ph.c * gm.gy, az = ph.c * gm.gz;
 #pragma unroll
@@ -1306,11 +1311,11 @@ __global__ __launch_bounds__(BLOCK) void k_init_adjoint(
       const double by = inflow ? in.by : beta0[cells + c.idx];
       const double bz = inflow ? in.bz : beta0[2 * cells + c.idx];
       const double g2 = 1.0 / (1.0 - (bx * bx + by * by + bz * bz));
-      const double W = (4.0 / 3.0) * e * g2;
+      const double W = ph.wfac * e * g2;
       const EqCoef<T> k = eq_coef<T>(ph, 0.0, e, W, bx, by, bz);
       const LamEq L = lam_eq(lam_sums(lam, k), ph, W, bx, by, bz);
       double gr[4];
-      eq_param_grad(L, e, bx, by, bz, gr);
+      eq_param_grad(ph, L, e, bx, by, bz, gr);
       if (inflow) {
         for (int k2 = 0; k2 < 4; ++k2) acc[1 + k2] = gr[k2];
       } else {

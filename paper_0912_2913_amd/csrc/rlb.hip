@@ -852,8 +852,6 @@ rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *la
                             double *dL_de_in) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
-  if (h->ph.gen_eos)
-    return fail(RLB_EINVAL, "the reverse mode is built for e = 3P (kappa = 1/3)");
   if (h->ph.eta_s > 0.0)
     return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   if (!g_state_t || !lam_next || !lam_out || lam_next == lam_out)
@@ -873,8 +871,6 @@ rlb_status rlb_adjoint_sweep(rlb_solver *h, const void *g_seq, int64_t seq_strid
                              void *lam_a, void *lam_b, void **lam_result) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
-  if (h->ph.gen_eos)
-    return fail(RLB_EINVAL, "the reverse mode is built for e = 3P (kappa = 1/3)");
   if (h->ph.eta_s > 0.0)
     return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   if (n < 0 || !lam_a || !lam_b || lam_a == lam_b || !lam_result || (n > 0 && !g_seq) ||
@@ -966,8 +962,6 @@ rlb_status rlb_moments_adjoint(rlb_solver *h, const void *g_state_T, const doubl
                                const double *dL_dbeta, void *lam_T) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
-  if (h->ph.gen_eos)
-    return fail(RLB_EINVAL, "the reverse mode is built for e = 3P (kappa = 1/3)");
   if (!g_state_T || !dL_de || !dL_dbeta || !lam_T)
     return fail(RLB_EINVAL, "a required pointer is NULL");
   RLB_DISPATCH(h, launch_moments_adjoint, h, g_state_T, dL_de, dL_dbeta, lam_T);
@@ -978,8 +972,6 @@ rlb_status rlb_init_adjoint(rlb_solver *h, const double *e0, const double *beta0
                             double *dL_dbeta_in, double *dL_de_in) {
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
-  if (h->ph.gen_eos)
-    return fail(RLB_EINVAL, "the reverse mode is built for e = 3P (kappa = 1/3)");
   if (!e0 || !beta0 || !lam_0 || !dL_de0 || !dL_dbeta0)
     return fail(RLB_EINVAL, "a required pointer is NULL");
   RLB_DISPATCH(h, launch_init_adjoint, h, e0, beta0, lam_0, dL_de0, dL_dbeta0, dL_dbeta_in,
