@@ -164,22 +164,28 @@ def bench_forward(s, steps, warmup):
     return dt, counts
 
 
-def bench_adjoint(s, T, warmup, reps=4):
-    """Cost of the gradient of a T-step run with sqrt(T) checkpointing, per step,
-    against one forward f+g step: the checkpointed g-only forward (one library
-    call per segment) plus the reverse sweep (per segment one recompute call and
-    one adjoint-sweep call; the parameter partials are reduced once at the end).
-    Also the adjoint kernels alone (one sweep over a segment's states)."""
+def _round(v):
+    return round(v, 4) if isinstance(v, float) else v
+
+
+def bench_adjoint(s, T, warmup, reps=4, mode="sqrt"):
+    """Cost of the gradient of a T-step run with sqrt(T) checkpointing (or the
+    3-level schedule), per step, against one forward f+g step: the checkpointed
+    g-only forward (one library call per segment) plus the reverse sweep (per
+    innermost segment one recompute call and one adjoint-sweep call; the
+    parameter partials are reduced once at the end).  Also the adjoint kernels
+    alone (one sweep over an innermost segment's states)."""
     import torch
 
-    from paper_0912_2913_amd.autograd import GRun, segment_length
+    from paper_0912_2913_amd.autograd import GRun, peak_states, schedule
     from paper_0912_2913_amd.solver import Solver
 
     sv = Solver(s)
     sv.step(warmup)
     fwd = time_steps(sv.step, 50, sv.stream) / 50
-    S = segment_length(T)
-    run = GRun(sv, T, S)
+    lens = schedule(T, mode)
+    S = lens[-1]
+    run = GRun(sv, T, lens)
     dLde = torch.full((sv.cells,), 1e-3, dtype=torch.float64, device=sv.device)
     dLdb = torch.full((3, sv.cells), 1e-3, dtype=torch.float64, device=sv.device)
 
@@ -211,7 +217,8 @@ def bench_adjoint(s, T, warmup, reps=4):
     sv.close()
     del sv, run, seq, la, lb
     torch.cuda.empty_cache()
-    return {"T": T, "segment": S, "forward_ms": 1e3 * fwd,
+    return {"T": T, "segment": S, "segments": lens, "states": peak_states(T, mode),
+            "forward_ms": 1e3 * fwd,
             "checkpointed_g_forward_ms": 1e3 * t_gf, "reverse_sweep_ms": 1e3 * t_bw,
             "adjoint_ms": 1e3 * t_sw, "ratio": t_bw / fwd, "gradient_ratio": (t_gf + t_bw) / fwd,
             "adjoint_kernel_ratio": t_sw / fwd}
@@ -341,7 +348,9 @@ def main():
         # reverse sweep per step (recompute + adjoint) against one forward step
         for st in (ri.F64, ri.F32):
             out["adjoint_sphere_" + ri.STORAGE_NAMES[st]] = {
-                k: round(v, 4) for k, v in bench_adjoint(ri.sphere(storage=st), 60, 5).items()}
+                k: _round(v) for k, v in bench_adjoint(ri.sphere(storage=st), 60, 5).items()}
+        out["adjoint_sphere_f64_3level"] = {
+            k: _round(v) for k, v in bench_adjoint(ri.sphere(), 60, 5, mode="3level").items()}
         out["tube_batch_64x2048_f32"] = bench_tubes()
         # in-place (AA-pattern) streaming: one state buffer instead of two
         sp = ri.sphere()

@@ -15,6 +15,13 @@ Schedule for T steps with segment length S (default ceil(sqrt(T))):
               the initial fields.
 Peak storage: K checkpoints + S segment states + 2 lambda buffers.  S = T keeps
 every state (store-all).
+
+When even 2 sqrt(T) states do not fit, "3level" nests one more level: segments
+of L1 = ceil(T^(2/3)) steps are split into sub-segments of L2 = ceil(T^(1/3))
+steps whose checkpoints are recomputed per segment in the backward pass, so that
+about 3 T^(1/3) states are held for one more g-only forward pass.  Every
+schedule gives the same gradient bit for bit (the recompute is bit-identical
+and the reverse partials accumulate in step order whatever the split).
 """
 from __future__ import annotations
 
@@ -28,23 +35,61 @@ import torch
 from .solver import Solver
 
 
-def segment_length(T: int, mode="sqrt") -> int:
+def _iroot(T: int, k: int) -> int:
+    """Smallest r >= 1 with r**k >= T."""
+    r = max(1, int(round(T ** (1.0 / k))))
+    while r ** k < T:
+        r += 1
+    while r > 1 and (r - 1) ** k >= T:
+        r -= 1
+    return r
+
+
+def schedule(T: int, mode="sqrt") -> List[int]:
+    """Segment lengths from the outermost level in: [S] for "sqrt" (S =
+    ceil(sqrt(T))), "store_all" ([T]) or an int segment length; [L1, L2] with
+    L1 = ceil(T^(2/3)) and L2 = ceil(T^(1/3)) for "3level"."""
     if T <= 0:
-        return 1
+        return [1]
     if mode == "store_all":
-        return T
-    if isinstance(mode, int):
-        return max(1, min(T, mode))
-    return max(1, int(math.ceil(math.sqrt(T))))
+        return [T]
+    if isinstance(mode, int) and not isinstance(mode, bool):
+        return [max(1, min(T, mode))]
+    if mode == "sqrt":
+        return [_iroot(T, 2)]
+    if mode == "3level":
+        l2 = _iroot(T, 3)
+        return [min(T, l2 * l2), l2]
+    raise ValueError(f"unknown checkpoint schedule {mode!r}")
+
+
+def segment_length(T: int, mode="sqrt") -> int:
+    return schedule(T, mode)[0]
+
+
+def peak_states(T: int, mode="sqrt") -> int:
+    """g states held at once by the schedule (checkpoints of every level plus
+    the innermost segment's recomputed states), lambda buffers excluded."""
+    lens = schedule(T, mode)
+    outer = [T] + lens
+    n = 0
+    for lv, L in enumerate(lens):
+        n += (outer[lv] + L - 1) // L  # checkpoints of this level (its first is the level above's)
+    return n + lens[-1]
 
 
 class GRun:
     """A g-only forward run of T steps on one solver with checkpoints."""
 
-    def __init__(self, solver: Solver, T: int, seg: int):
+    def __init__(self, solver: Solver, T: int, seg):
+        """seg: the segment length, or the list of segment lengths from the
+        outermost level in (see schedule())."""
         self.sv = solver
         self.T = int(T)
-        self.S = int(seg)
+        self.lens = [int(v) for v in (seg if isinstance(seg, (list, tuple)) else [seg])]
+        if any(v < 1 for v in self.lens) or any(b > a for a, b in zip(self.lens, self.lens[1:])):
+            raise ValueError("segment lengths must be >= 1 and non-increasing")
+        self.S = self.lens[0]
         self.K = (self.T + self.S - 1) // self.S if self.T > 0 else 1
         self.ckpt: List[torch.Tensor] = []
         self.final: Optional[torch.Tensor] = None
@@ -82,18 +127,22 @@ class GRun:
         dtau = torch.zeros(sv.batch, dtype=torch.float64, device=dev)
         dbin = torch.zeros(3, dtype=torch.float64, device=dev)
         dein = torch.zeros(1, dtype=torch.float64, device=dev)
-        la, lb = sv.new_lam(), sv.new_lam()
-        sv.moments_adjoint(self.final, dLde.contiguous(), dLdb.contiguous(), la)
-        seq = sv.new_g_seq(min(self.S, max(self.T, 1)))
+        self._lam = [sv.new_lam(), sv.new_lam()]
+        sv.moments_adjoint(self.final, dLde.contiguous(), dLdb.contiguous(), self._lam[0])
+        self._seq = sv.new_g_seq(min(self.lens[-1], max(self.T, 1)))
+        # per inner level: two fixed buffers to advance between (one cached
+        # graph serves every sub-segment) and its checkpoint buffers
+        self._inner = []
+        for lv in range(1, len(self.lens)):
+            kmax = (self.lens[lv - 1] + self.lens[lv] - 1) // self.lens[lv]
+            self._inner.append(([sv.new_g(), sv.new_g(), sv.new_g()],
+                                [sv.new_g() for _ in range(kmax - 1)]))
         for k in range(self.K - 1, -1, -1):
             n = min(self.S, self.T - k * self.S)
-            if n <= 0:
-                continue
-            seq[0].copy_(self.ckpt[k])
-            sv.trajectory_g(seq, n)
-            res = sv.adjoint_sweep(seq, n, la, lb)
-            if res is lb:
-                la, lb = lb, la
+            if n > 0:
+                self._reverse(self.ckpt[k], n, 1)
+        la = self._lam[0]
+        self._seq = self._inner = None
         sv.adjoint_flush(dtau, dbin, dein)
         dtc = None
         if sv.tau_cell is not None:
@@ -102,7 +151,37 @@ class GRun:
         de0 = torch.empty(sv.cells, dtype=torch.float64, device=dev)
         db0 = torch.empty((3, sv.cells), dtype=torch.float64, device=dev)
         sv.init_adjoint(la, de0, db0, dbin, dein)
+        self._lam = None
         return dtau, dein, dbin, de0, db0, dtc
+
+    def _reverse(self, start: torch.Tensor, n: int, lv: int):
+        """Adjoint steps down through the n steps that begin at state `start`
+        (lambda at their end in self._lam[0] on entry, at their beginning on
+        return).  Level lv splits them into sub-segments of self.lens[lv]
+        steps, recomputing the sub-segment checkpoints from `start`; past the
+        innermost level the n states are recomputed and swept."""
+        sv = self.sv
+        if lv >= len(self.lens):
+            seq = self._seq
+            seq[0].copy_(start)
+            sv.trajectory_g(seq, n)
+            la, lb = self._lam
+            if sv.adjoint_sweep(seq, n, la, lb) is lb:
+                self._lam = [lb, la]
+            return
+        L = self.lens[lv]
+        (a, b, tmp), bufs = self._inner[lv - 1]
+        m = (n + L - 1) // L
+        cks = [start]
+        if m > 1:
+            a.copy_(start)
+            for j in range(1, m):
+                sv.advance_g(a, b, tmp, L)
+                bufs[j - 1].copy_(b)
+                cks.append(bufs[j - 1])
+                a, b = b, a
+        for j in range(m - 1, -1, -1):
+            self._reverse(cks[j], min(L, n - j * L), lv + 1)
 
 
 class RLBFunction(torch.autograd.Function):
@@ -110,7 +189,8 @@ class RLBFunction(torch.autograd.Function):
     -> (e_T, beta_T).
 
     ``setup`` fixes everything else (extents, boundaries, storage, n0, solid);
-    ``steps`` is T and ``checkpoint`` is "sqrt", "store_all" or a segment length.
+    ``steps`` is T and ``checkpoint`` is "sqrt", "3level", "store_all" or a
+    segment length.
     With ``tau_cell`` the per-cell relaxation times replace tau (whose gradient
     is then the one for a uniform shift of each instance's field).  Inputs may
     live on any device; the run uses ``setup``'s GPU (cuda:0).
@@ -130,7 +210,7 @@ class RLBFunction(torch.autograd.Function):
         sv = Solver(s)
         if tau_cell is not None:
             sv.set_tau_field(tau_cell.detach())
-        run = GRun(sv, int(steps), segment_length(int(steps), checkpoint))
+        run = GRun(sv, int(steps), schedule(int(steps), checkpoint))
         need = any(ctx.needs_input_grad[:6])
         e, b = run.forward(keep=need)
         if not need:

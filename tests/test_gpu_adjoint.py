@@ -162,8 +162,9 @@ def test_checkpointed_equals_store_all_bitwise():
     r1 = _gpu_gradient(s, 30, "sqrt")
     r2 = _gpu_gradient(s, 30, "store_all")
     r3 = _gpu_gradient(s, 30, 7)
-    for x, y, z in zip(r1[1:], r2[1:], r3[1:]):
-        assert np.array_equal(x, y) and np.array_equal(x, z)
+    r4 = _gpu_gradient(s, 30, "3level")  # segments of 16 split into sub-segments of 4
+    for x, y, z, w in zip(r1[1:], r2[1:], r3[1:], r4[1:]):
+        assert np.array_equal(x, y) and np.array_equal(x, z) and np.array_equal(x, w)
 
 
 def test_gradient_matches_central_differences_fp64():
