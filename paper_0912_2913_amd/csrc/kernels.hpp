@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "codec.hpp"
 #include "lattice.hpp"
 
@@ -1555,14 +1557,49 @@ __global__ __launch_bounds__(BLOCK) void k_aa_local(const Geom g, const Phys ph,
   count_lanes(bad, counters, 0);
 }
 
+// f(std::integral_constant<int, q>) for q = 0 .. Q-1, each a separate
+// instance of the body.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_q_(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <class F>
+__device__ __forceinline__ void static_for_q(F &&f) {
+  static_for_q_(f, std::make_integer_sequence<int, Q>{});
+}
+
+// Solid flags of the 27 cells around c (offsets -1..1 per axis, each
+// resolved as a pull resolves its source: wrapped on periodic axes, clamped
+// on the others), bit (dz+1)*9 + (dy+1)*3 + (dx+1).  All 27 loads are issued
+// together, before the general path stores anything, so that none of its
+// decisions waits on a load behind a store.
+__device__ __forceinline__ unsigned solid_around(const Geom &g, const Phys &ph, const Cell &c) {
+  if (!ph.cls) return 0u;
+  unsigned m = 0u;
+  bool cl = false;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const long long i = cell_index(g, c.b, resolve(g, 0, c.x + dx, cl),
+                                       resolve(g, 1, c.y + dy, cl), resolve(g, 2, c.z + dz, cl));
+        if (ph.cls[i] & CLS_SOLID) m |= 1u << ((dz + 1) * 9 + (dy + 1) * 3 + (dx + 1));
+      }
+  return m;
+}
+
+__device__ __forceinline__ bool solid_off(unsigned m, int dx, int dy, int dz) {
+  return (m >> ((dz + 1) * 9 + (dy + 1) * 3 + (dx + 1))) & 1u;
+}
+
 // In-place pull step of one updated cell on the general path (listed cells:
 // near a solid, inflow, or on a face of a non-periodic axis).
 template <class Cd>
 __device__ __forceinline__ bool aa_pull_general(const Geom &g, const Phys &ph, const FaceMap &fm,
                                                 typename Cd::elem *__restrict__ A,
                                                 const typename Cd::elem *__restrict__ Fb,
-                                                const int *__restrict__ ftgt,
-                                                const int *__restrict__ frd,
                                                 const HeldEq<typename Cd::elem> &in_eq,
                                                 const Cell &c) {
   using T = typename Cd::calc;
@@ -1572,6 +1609,7 @@ __device__ __forceinline__ bool aa_pull_general(const Geom &g, const Phys &ph, c
   El *__restrict__ Ag = A + Q * qs;
   const bool inflow = is_inflow(g, c.x, c.y, c.z);
   const int co[3] = {c.x, c.y, c.z};
+  const unsigned sm = solid_around(g, ph, c);
   bool bad = false;
   T pf[Q], pg[Q];
   if (inflow) {
@@ -1583,7 +1621,11 @@ __device__ __forceinline__ bool aa_pull_general(const Geom &g, const Phys &ph, c
   } else {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const Pull p = pull_general(g, ph, c, q);
+      bool clamped = false;
+      const int sx = resolve(g, 0, c.x - EX[q], clamped);
+      const int sy = resolve(g, 1, c.y - EY[q], clamped);
+      const int sz = resolve(g, 2, c.z - EZ[q], clamped);
+      const bool bounce = solid_off(sm, -EX[q], -EY[q], -EZ[q]);
       // the first clamped axis names the face copy to read
       int a = -1, sd = 0;
 #pragma unroll
@@ -1595,74 +1637,70 @@ __device__ __forceinline__ bool aa_pull_general(const Geom &g, const Phys &ph, c
           sd = r < 0 ? 0 : 1;
         }
       }
-      if (p.clamped && !p.bounce && a >= 0) {  // bounce-back takes precedence
-        const long long rem = p.idx - (long long)c.b * g.per;
-        const int sx = (int)(rem % g.n[0]);
-        const int sy = (int)((rem / g.n[0]) % g.n[1]);
-        const int sz = (int)(rem / ((long long)g.n[0] * g.n[1]));
+      if (clamped && !bounce && a >= 0) {  // bounce-back takes precedence
         const long long t = face_pos(g, fm, fm.id[a][sd], a, c.b, sx, sy, sz);
         pf[q] = Cd::dec(Fb[(size_t)q * fm.nf + t]);
         pg[q] = Cd::dec(Fb[(size_t)(Q + q) * fm.nf + t]);
       } else {
-        // plain source: S(src)_q sits at slot opp(q); bounce-back
-        // (p.idx = c.idx, p.q = opp(q)): S(x)_opp(q) sits at slot q
-        const size_t o = at(OPP[p.q], p.idx);
+        // plain source: S(src)_q sits at slot opp(q); bounce-back: S(x)_opp(q)
+        // sits at slot q
+        const size_t o = bounce ? at(q, c.idx) : at(OPP[q], cell_index(g, c.b, sx, sy, sz));
         pf[q] = Cd::dec(Af[o]);
         pg[q] = Cd::dec(Ag[o]);
       }
     }
     bad = collide_inplace<Cd>(g, ph, c, pg, pf);
   }
-  // this cell's entry in the face-reader table (first face listing it)
-  long long ft = -1;
-  for (int f = 0; f < fm.count && ft < 0; ++f)
-    for (int a = 0; a < 3; ++a)
-      for (int sd = 0; sd < 2; ++sd)
-        if (fm.id[a][sd] == f && co[a] == (sd == 0 ? 0 : g.n[a] - 1))
-          ft = face_pos(g, fm, f, a, c.b, c.x, c.y, c.z);
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
+  // one instance of the body per direction (q a constant, so that pf[q] and
+  // pg[q] stay in registers and impossible clamp patterns fold away)
+  static_for_q([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int e[3] = {EX[q], EY[q], EZ[q]};
     const El vf = inflow ? in_eq.v[q] : Cd::enc(pf[q]);
     const El vg = inflow ? in_eq.v[Q + q] : Cd::enc(pg[q]);
-    // plain receiver x + e_q
-    int r[3];
-    bool in = true;
+    // Every reader whose pull of q resolves to this cell: along each axis in
+    // the clamp pattern m it sits on this cell's face and its pull leaves the
+    // domain there (clamped back onto this cell); along the other axes it is
+    // the plain neighbour co + e.  m = 0 is the plain receiver x + e_q.
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int e = a == 0 ? EX[q] : (a == 1 ? EY[q] : EZ[q]);
-      r[a] = co[a] + e;
-      if (g.periodic[a]) {
-        if (r[a] < 0) r[a] += g.n[a];
-        if (r[a] >= g.n[a]) r[a] -= g.n[a];
-      } else if (r[a] < 0 || r[a] >= g.n[a]) {
-        in = false;
+    for (int m = 0; m < 8; ++m) {
+      if ((m & 1) && e[0] == 0) continue;
+      if ((m & 2) && e[1] == 0) continue;
+      if ((m & 4) && e[2] == 0) continue;
+      bool ok = true;
+      int rc[3], off[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int n = g.n[d];
+        if ((m >> d) & 1) {
+          ok = ok && !g.periodic[d] &&
+               ((e[d] == 1 && co[d] == 0) || (e[d] == -1 && co[d] == n - 1));
+          rc[d] = co[d];
+          off[d] = 0;
+        } else {
+          int r = co[d] + e[d];
+          if (g.periodic[d]) {
+            if (r < 0) r += n;
+            if (r >= n) r -= n;
+          } else {
+            ok = ok && r >= 0 && r < n;
+          }
+          rc[d] = r;
+          off[d] = e[d];
+        }
       }
-    }
-    if (in) {
-      const long long ri = cell_index(g, c.b, r[0], r[1], r[2]);
-      if (!solid_at(ph, ri) && !is_inflow(g, r[0], r[1], r[2])) {
-        Af[at(q, ri)] = vf;
-        Ag[at(q, ri)] = vg;
+      if (ok && !solid_off(sm, off[0], off[1], off[2]) && !is_inflow(g, rc[0], rc[1], rc[2])) {
+        const size_t o = at(q, cell_index(g, c.b, rc[0], rc[1], rc[2]));
+        Af[o] = vf;
+        Ag[o] = vg;
       }
     }
     // bounce-back receiver: this cell, when its pull of opp(q) hits a solid
-    if (!inflow && pull_general(g, ph, c, OPP[q]).bounce) {
+    if (!inflow && solid_off(sm, e[0], e[1], e[2])) {
       Af[at(OPP[q], c.idx)] = vf;
       Ag[at(OPP[q], c.idx)] = vg;
     }
-    // readers whose pull of q is clamped onto this cell
-    if (ft >= 0 && q > 0) {
-      const size_t k = (size_t)ft * (Q - 1) + (q - 1);
-      if (ftgt[k] >= 0)
-        for (int m = 0; m < 7; ++m) {
-          const int ri = frd[k * 7 + m];
-          if (ri >= 0) {
-            Af[at(q, ri)] = vf;
-            Ag[at(q, ri)] = vg;
-          }
-        }
-    }
-  }
+  });
   return bad;
 }
 
@@ -1677,8 +1715,6 @@ __global__ __launch_bounds__(BLOCK) void k_aa_pull_all(const Geom g, const Phys 
                                                        const int *__restrict__ list,
                                                        typename Codec<ST, TC>::elem *__restrict__ A,
                                                        const typename Codec<ST, TC>::elem *__restrict__ Fb,
-                                                       const int *__restrict__ ftgt,
-                                                       const int *__restrict__ frd,
                                                        const HeldEq<typename Codec<ST, TC>::elem> in_eq,
                                                        unsigned long long *__restrict__ counters) {
   using Cd = Codec<ST, TC>;
@@ -1687,7 +1723,7 @@ __global__ __launch_bounds__(BLOCK) void k_aa_pull_all(const Geom g, const Phys 
   bool bad = false;
   if ((int)blockIdx.x < nlist) {
     const int li = list[(size_t)blockIdx.x * BLOCK + threadIdx.x];
-    if (li >= 0) bad = aa_pull_general<Cd>(g, ph, fm, A, Fb, ftgt, frd, in_eq, cell_at(g, li));
+    if (li >= 0) bad = aa_pull_general<Cd>(g, ph, fm, A, Fb, in_eq, cell_at(g, li));
   } else {
     const Cell c = decode_cell(g, (int)blockIdx.x - nlist);
     if (c.active && aa_plain(g, ph, c)) {

@@ -263,8 +263,8 @@ rlb_status launch_steps(rlb_solver *h, int nsteps) {
         // listed cells (general path) and the rest (fast path) in one launch
         hipLaunchKernelGGL((k_aa_pull_all<ST, TC>), dim3(h->n_aablk + grid_blocks(h)), dim3(BLOCK),
                            0, h->stream, h->g, h->ph, h->fm, h->n_aablk,
-                           (const int *)h->d_aalist, A, (const El *)h->d_fb,
-                           (const int *)h->d_ftgt, (const int *)h->d_frd, in_eq, h->d_counters);
+                           (const int *)h->d_aalist, A, (const El *)h->d_fb, in_eq,
+                           h->d_counters);
       } else
         hipLaunchKernelGGL((k_aa_local<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream,
                            h->g, h->ph, h->fm, A, (El *)h->d_fb, in_eq, h->d_counters);
@@ -756,7 +756,7 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
     if (fm.nf > 0 &&
         (e = hipMalloc(&h->d_fb, (size_t)2 * Q * fm.nf * h->elem)) != hipSuccess)
       return cleanup_fail(e, "hipMalloc(face copies)");
-    if ((s = build_faces_table(h)) != RLB_OK || (s = build_aa_list(h)) != RLB_OK) {
+    if ((s = build_aa_list(h)) != RLB_OK) {
       free_solver(h);
       return s;
     }
