@@ -1529,30 +1529,24 @@ __global__ __launch_bounds__(BLOCK) void k_aa_local(const Geom g, const Phys ph,
     El *__restrict__ Af = A;
     El *__restrict__ Ag = A + Q * qs;
     const bool face = fm.count > 0 && !aa_plain(g, ph, c);
-    if (is_inflow(g, c.x, c.y, c.z)) {
+    // Inflow cells run the common path and store their held values instead
+    // of the collision's (no divergent branch in the waves that hold them).
+    const bool inflow = is_inflow(g, c.x, c.y, c.z);
+    T pf[Q], pg[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        Af[at(OPP[q], c.idx)] = in_eq.v[q];
-        Ag[at(OPP[q], c.idx)] = in_eq.v[Q + q];
-      }
-      if (face)
-        aa_face_copies(g, fm, c, Fb, [&](int q) { return in_eq.v[q]; },
-                       [&](int q) { return in_eq.v[Q + q]; });
-    } else {
-      T pf[Q], pg[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        pf[q] = Cd::dec(Af[at(q, c.idx)]);
-        pg[q] = Cd::dec(Ag[at(q, c.idx)]);
-      }
-      bad = collide_emit<Cd>(
-          ph, c, pg, pf, [&](int q, El v) { Ag[at(OPP[q], c.idx)] = v; },
-          [&](int q, El v) { Af[at(OPP[q], c.idx)] = v; });
-      // face cells copy what they just stored (same thread: reads see the writes)
-      if (face)
-        aa_face_copies(g, fm, c, Fb, [&](int q) { return Af[at(OPP[q], c.idx)]; },
-                       [&](int q) { return Ag[at(OPP[q], c.idx)]; });
+    for (int q = 0; q < Q; ++q) {
+      pf[q] = Cd::dec(Af[at(q, c.idx)]);
+      pg[q] = Cd::dec(Ag[at(q, c.idx)]);
     }
+    bad = collide_emit<Cd>(
+              ph, c, pg, pf,
+              [&](int q, El v) { Ag[at(OPP[q], c.idx)] = inflow ? in_eq.v[Q + q] : v; },
+              [&](int q, El v) { Af[at(OPP[q], c.idx)] = inflow ? in_eq.v[q] : v; }) &&
+          !inflow;
+    // face cells copy what they just stored (same thread: reads see the writes)
+    if (face)
+      aa_face_copies(g, fm, c, Fb, [&](int q) { return Af[at(OPP[q], c.idx)]; },
+                     [&](int q) { return Ag[at(OPP[q], c.idx)]; });
   }
   count_lanes(bad, counters, 0);
 }
