@@ -1361,7 +1361,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify(const Geom g, const uint8_t 
 //     post-collision S(x)_q to each cell that will pull it: the plain
 //     neighbour x + e_q, x itself (slot opp(q)) when x's pull of opp(q)
 //     bounces off a solid, and the readers whose pull of q is clamped onto
-//     x (from the face-reader table).  Each location of A is read and
+//     x (enumerated per clamp pattern).  Each location of A is read and
 //     written by the same cell only, so the kernel is race-free in place.
 // A value needed by two readers, a face cell's S(x)_q pulled both by its
 // plain neighbour and by a face reader whose pull is clamped onto x, is
