@@ -8,13 +8,14 @@ alone: every checkpoint and recomputed state is a g block in the solver's
 storage format, and the recompute is bit-identical to the forward.
 
 Schedule for T steps with segment length S (default ceil(sqrt(T))):
-  forward  -- g-only steps from S_0; keep S_0, S_S, S_2S, ... (K = ceil(T/S));
+  forward  -- g-only steps from S_0; keep S_0, S_S, S_2S, ... (K = ceil(T/S)),
+              each segment advancing straight into the next checkpoint;
   backward -- lambda_T from the moment map; for each segment from the last:
-              restore its checkpoint, recompute and keep its S states, then run
-              the adjoint steps down through the segment; finally map lambda_0 to
-              the initial fields.
-Peak storage: K checkpoints + S segment states + 2 lambda buffers.  S = T keeps
-every state (store-all).
+              recompute its S - 1 later states from its checkpoint (read in
+              place, not copied), then run the adjoint steps down through the
+              segment; finally map lambda_0 to the initial fields.
+Peak storage: K checkpoints + S - 1 segment states + 2 lambda buffers.  S = T
+keeps every state (store-all).
 
 When even 2 sqrt(T) states do not fit, "3level" nests one more level: segments
 of L1 = ceil(T^(2/3)) steps are split into sub-segments of L2 = ceil(T^(1/3))
@@ -69,13 +70,14 @@ def segment_length(T: int, mode="sqrt") -> int:
 
 def peak_states(T: int, mode="sqrt") -> int:
     """g states held at once by the schedule (checkpoints of every level plus
-    the innermost segment's recomputed states), lambda buffers excluded."""
+    the innermost segment's recomputed states after its checkpoint), lambda
+    and ping-pong buffers excluded."""
     lens = schedule(T, mode)
     outer = [T] + lens
     n = 0
     for lv, L in enumerate(lens):
         n += (outer[lv] + L - 1) // L  # checkpoints of this level (its first is the level above's)
-    return n + lens[-1]
+    return n + lens[-1] - 1
 
 
 class GRun:
@@ -105,17 +107,17 @@ class GRun:
             self.final = sv.new_g()
             sv.advance_g(s0, self.final, tmp, self.T)
             return sv.fields_g(self.final)
-        # advance between two fixed buffers (the library replays one cached
-        # graph per buffer pair and segment length) and copy out checkpoints
+        # each segment advances straight into the next checkpoint's buffer
         self.ckpt = [s0]
-        a, b = s0.clone(), sv.new_g()
+        cur = s0
         for k in range(self.K):
             n = min(self.S, self.T - k * self.S)
-            sv.advance_g(a, b, tmp, max(n, 0))
+            nxt = sv.new_g()
+            sv.advance_g(cur, nxt, tmp, max(n, 0))
             if k + 1 < self.K:
-                self.ckpt.append(b.clone())
-            a, b = b, a
-        self.final = a
+                self.ckpt.append(nxt)
+            cur = nxt
+        self.final = cur
         return sv.fields_g(self.final)
 
     def backward(self, dLde: torch.Tensor, dLdb: torch.Tensor):
@@ -129,14 +131,14 @@ class GRun:
         dein = torch.zeros(1, dtype=torch.float64, device=dev)
         self._lam = [sv.new_lam(), sv.new_lam()]
         sv.moments_adjoint(self.final, dLde.contiguous(), dLdb.contiguous(), self._lam[0])
-        self._seq = sv.new_g_seq(min(self.lens[-1], max(self.T, 1)))
-        # per inner level: two fixed buffers to advance between (one cached
-        # graph serves every sub-segment) and its checkpoint buffers
+        # the innermost segment's states after its first (which is the
+        # checkpoint itself, read in place)
+        self._seq = sv.new_g_seq(max(1, min(self.lens[-1], max(self.T, 1)) - 1))
+        # per inner level: a ping-pong buffer and its checkpoint buffers
         self._inner = []
         for lv in range(1, len(self.lens)):
             kmax = (self.lens[lv - 1] + self.lens[lv] - 1) // self.lens[lv]
-            self._inner.append(([sv.new_g(), sv.new_g(), sv.new_g()],
-                                [sv.new_g() for _ in range(kmax - 1)]))
+            self._inner.append((sv.new_g(), [sv.new_g() for _ in range(kmax - 1)]))
         for k in range(self.K - 1, -1, -1):
             n = min(self.S, self.T - k * self.S)
             if n > 0:
@@ -162,24 +164,25 @@ class GRun:
         innermost level the n states are recomputed and swept."""
         sv = self.sv
         if lv >= len(self.lens):
+            # states start+1 .. start+n-1 into the sequence buffer, their n-1
+            # reverse steps, then the reverse step of `start` read in place
             seq = self._seq
-            seq[0].copy_(start)
-            sv.trajectory_g(seq, n)
             la, lb = self._lam
-            if sv.adjoint_sweep(seq, n, la, lb) is lb:
-                self._lam = [lb, la]
+            if n > 1:
+                sv.step_g(start, seq[0])
+                sv.trajectory_g(seq, n - 1)
+                if sv.adjoint_sweep(seq, n - 1, la, lb) is lb:
+                    la, lb = lb, la
+            sv.adjoint_step(start, la, lb)
+            self._lam = [lb, la]
             return
         L = self.lens[lv]
-        (a, b, tmp), bufs = self._inner[lv - 1]
+        tmp, bufs = self._inner[lv - 1]
         m = (n + L - 1) // L
         cks = [start]
-        if m > 1:
-            a.copy_(start)
-            for j in range(1, m):
-                sv.advance_g(a, b, tmp, L)
-                bufs[j - 1].copy_(b)
-                cks.append(bufs[j - 1])
-                a, b = b, a
+        for j in range(1, m):
+            sv.advance_g(cks[-1], bufs[j - 1], tmp, L)
+            cks.append(bufs[j - 1])
         for j in range(m - 1, -1, -1):
             self._reverse(cks[j], min(L, n - j * L), lv + 1)
 

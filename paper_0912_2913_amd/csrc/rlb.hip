@@ -12,9 +12,11 @@
 #include "kernels.hpp"
 
 // Loop entry points with at least this many steps replay a cached HIP graph
-// of their launches (kernels only) instead of launching step by step.
+// of their launches (kernels only), from the second call with the same
+// arguments on, instead of launching step by step.
 constexpr int kGraphMin = 4;
 constexpr int kGraphSlots = 12;
+constexpr int kSeenSlots = 16;
 
 using namespace rlb;
 
@@ -69,8 +71,8 @@ struct rlb_solver {
     int64_t stride;
     int n;
     hipGraphExec_t exec;
-  } graphs[kGraphSlots];
-  int graph_next;
+  } graphs[kGraphSlots], seen[kSeenSlots];  // seen: keys launched once, not captured
+  int graph_next, seen_next;
 };
 
 namespace {
@@ -395,9 +397,11 @@ void drop_graphs(rlb_solver *h) {
 }
 
 // Run `body` (which launches on h->stream) through a cached graph keyed by
-// (kind, a, b, c, stride, n): captured on a private stream the first time,
-// replayed on h->stream afterwards.  Kernel arguments (geometry, physics,
-// buffers) are fixed at capture; anything that changes them drops the cache.
+// (kind, a, b, c, stride, n): launched directly the first time a key is seen,
+// captured on a private stream the second time, replayed on h->stream
+// afterwards (calls whose buffers never repeat pay no capture).  Kernel
+// arguments (geometry, physics, buffers) are fixed at capture; anything that
+// changes them drops the cache.
 template <class F>
 rlb_status run_graph(rlb_solver *h, int kind, const void *a, const void *b, const void *c,
                      int64_t stride, int n, F body) {
@@ -407,6 +411,19 @@ rlb_status run_graph(rlb_solver *h, int kind, const void *a, const void *b, cons
       RLB_HIP(hipGraphLaunch(G.exec, h->stream));
       return RLB_OK;
     }
+  }
+  bool seen = false;
+  for (int i = 0; i < kSeenSlots && !seen; ++i) {
+    auto &K = h->seen[i];
+    if (K.kind == kind && K.a == a && K.b == b && K.c == c && K.stride == stride && K.n == n) {
+      seen = true;
+      K.kind = 0;
+    }
+  }
+  if (!seen) {
+    h->seen[h->seen_next] = {kind, a, b, c, stride, n, nullptr};
+    h->seen_next = (h->seen_next + 1) % kSeenSlots;
+    return body();
   }
   if (!h->cap) RLB_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
   hipStream_t user = h->stream;

@@ -342,9 +342,11 @@ def test_loop_entry_points_reject_bad_arguments():
 
 
 def test_graph_replays_match_step_by_step_launches():
-    """Loop entry points of 4 or more steps replay a cached graph: every replay,
-    with other work and synchronisations in between, matches the step-by-step
-    result bitwise (advance, trajectory, sweep; the sweep's partials too)."""
+    """Loop entry points of 4 or more steps launch directly the first time a
+    call's arguments are seen, capture a graph the second time and replay it
+    afterwards: every repetition, with other work and synchronisations in
+    between, matches the step-by-step result bitwise (advance, trajectory,
+    sweep; the sweep's partials too)."""
     from paper_0912_2913_amd.solver import Solver
 
     s = setups()["inflow_outflow_obstacle"]
@@ -373,7 +375,8 @@ def test_graph_replays_match_step_by_step_launches():
         sv.adjoint_step(seq_ref[j], a, b, *(g_ref if j == 0 else (None, None, None)))
         a, b = b, a
     lam_ref = sv.unpack(a).cpu()
-    for rep in range(3):
+    la, lb = sv.new_lam(), sv.new_lam()
+    for rep in range(4):
         dst.fill_(float(rep))
         sv.advance_g(g0, dst, tmp, 6)
         assert torch.equal(bits(sv.unpack(dst)[:, fl]), bits(sv.unpack(ref[6])[:, fl])), rep
@@ -384,7 +387,8 @@ def test_graph_replays_match_step_by_step_launches():
             assert torch.equal(bits(sv.unpack(seq[j])[:, fl]), bits(sv.unpack(seq_ref[j])[:, fl])), (rep, j)
         torch.cuda.synchronize()
         _ = (dst * 2).sum().item()  # unrelated eager work between replays
-        la, lb = lam_T.clone(), sv.new_lam().fill_(float("nan"))
+        la.copy_(lam_T)
+        lb.fill_(float("nan"))
         res = sv.adjoint_sweep(seq, 6, la, lb)
         g_sw = (z(s.batch), z(3), z(1))
         sv.adjoint_flush(*g_sw)
