@@ -224,6 +224,38 @@ def bench_adjoint(s, T, warmup, reps=4, mode="sqrt"):
             "adjoint_kernel_ratio": t_sw / fwd}
 
 
+def bench_large_gradient(T=4000, modes=("sqrt", "3level")):
+    """The memory plan at scale: a T-step gradient of the surface pressure on the
+    384x192x192 FP32 sphere (g-only checkpoints of 1.08 GB each) through the
+    differentiable run, per schedule: wall time, peak device memory and states
+    held.  At c_l = 1 this set-up goes unphysical after ~125 steps (the scheme
+    as published), so the figures are time and memory, not a gradient value."""
+    import torch
+
+    import rlb_inputs as ri
+    from paper_0912_2913_amd.autograd import peak_states, rlb_run, surface_mask
+
+    s = ri.sphere_large(steps=T, storage=ri.F32)
+    mask = torch.as_tensor(surface_mask(s), device="cuda")
+    g_bytes = Q * s.cells * 4
+    out = {"T": T, "cells": s.cells, "g_state_GB": round(g_bytes / 1e9, 3)}
+    for mode in modes:
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        t0 = time.perf_counter()
+        tau = torch.tensor(s.tau, device="cuda", requires_grad=True)
+        e, _ = rlb_run(s, T, tau=tau, checkpoint=mode)
+        (e[mask] / 3.0).sum().backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[mode] = {"seconds": round(dt, 2), "ms_per_step": round(1e3 * dt / T, 3),
+                     "peak_GB": round(torch.cuda.max_memory_allocated() / 1e9, 1),
+                     "states": peak_states(T, mode)}
+        del e, tau
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_tubes(T=2000):
     """64 shock tubes of 2048 cells in one lattice (FP32): launch-bound, so the
     figures are microseconds per step and the wall time of a T-step gradient
@@ -367,6 +399,7 @@ def main():
         out["adjoint_sphere_f64_3level"] = {
             k: _round(v) for k, v in bench_adjoint(ri.sphere(), 60, 5, mode="3level").items()}
         out["tube_batch_64x2048_f32"] = bench_tubes()
+        out["gradient_large_sphere_f32_T4000"] = bench_large_gradient()
         # in-place (AA-pattern) streaming: one state buffer instead of two
         sp = ri.sphere()
         sp.inplace = True
