@@ -19,15 +19,6 @@ using LamT = double;
 
 enum { ST_F64 = 0, ST_F32 = 1, ST_F32DEV = 2, ST_F16DEV = 3, ST_BF16DEV = 4 };
 
-// bfloat16 = the upper 16 bits of an IEEE binary32.  Encoding rounds to
-// nearest, ties to even, on the discarded 16 bits; NaNs stay (quiet) NaNs.
-__device__ inline uint16_t f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x0040u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
 template <int ST>
 struct Format;
 
@@ -68,6 +59,9 @@ struct Format<ST_F16DEV> {
   __device__ static elem enc(float v) { return (_Float16)v; }
 };
 
+// bfloat16 = the upper 16 bits of an IEEE binary32.  Encoding rounds to
+// nearest, ties to even, on the discarded 16 bits (gfx950's conversion
+// instruction); NaNs stay quiet NaNs.
 template <>
 struct Format<ST_BF16DEV> {
   using elem = uint16_t;
@@ -75,7 +69,7 @@ struct Format<ST_BF16DEV> {
   template <class T>
   __device__ static T dec(elem v) { return (T)__uint_as_float((uint32_t)v << 16); }
   // only FP32 compute is paired with this format
-  __device__ static elem enc(float v) { return f32_to_bf16_rne(v); }
+  __device__ static elem enc(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 };
 
 template <int ST, class TC>
