@@ -150,7 +150,11 @@ rlb_status rlb_step_g(rlb_solver *h, const void *g_src, void *g_dst);
  * g_dst (n = 0 copies g_src to g_dst).  g_src is read only; g_tmp (needed
  * for n > 1) is overwritten; the three buffers are distinct g blocks.  Solid
  * and padding entries as in rlb_step_g (copied when n = 0).  One
- * call replaces n host round trips (the checkpointed forward sweep). */
+ * call replaces n host round trips (the checkpointed forward sweep).
+ * Loop calls (this one, rlb_trajectory_g, rlb_adjoint_sweep) of n >= 4 are
+ * replayed from a HIP graph that the library captures on the second call
+ * with the same buffers and n; the graph holds the pointers, not the data.
+ * rlb_set_tau_field and rlb_hold_eta_over_s drop the captured graphs. */
 rlb_status rlb_advance_g(rlb_solver *h, const void *g_src, void *g_dst, void *g_tmp,
                          int32_t n);
 
