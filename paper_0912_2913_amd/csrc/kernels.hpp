@@ -1242,15 +1242,19 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_faces(long long npairs,
                                                          Lm *__restrict__ lam_out) {
   const long long k = (long long)blockIdx.x * BLOCK + threadIdx.x;
   if (k >= npairs) return;
+  // the target and the 7 readers are loaded together (one round trip)
   const int yi = tgt[k];
+  int r[7];
+#pragma unroll
+  for (int m = 0; m < 7; ++m) r[m] = rd[k * 7 + m];
   if (yi < 0) return;
   const int p = (int)(k % (Q - 1)) + 1;
   Lm acc = (Lm)0;
   bool any = false;
+#pragma unroll
   for (int m = 0; m < 7; ++m) {
-    const int ri = rd[k * 7 + m];
-    if (ri >= 0) {
-      acc += scratch[at(p, ri)];
+    if (r[m] >= 0) {
+      acc += scratch[at(p, r[m])];
       any = true;
     }
   }
