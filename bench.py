@@ -297,6 +297,9 @@ def main():
     ap.add_argument("--reverse-only", action="store_true",
                     help="only the 60-step FP64 sphere gradient schedule (for kernel traces of "
                          "the reverse step)")
+    ap.add_argument("--inplace-only", action="store_true",
+                    help="only the FP64 sphere with in-place streaming, 200 steps (for kernel "
+                         "traces of the in-place kernels)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the stream-collide step is not run across "
@@ -308,6 +311,14 @@ def main():
     import rlb_inputs as ri
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.inplace_only:
+        sp = ri.sphere()
+        sp.inplace = True
+        dta, cnt = bench_forward(sp, 200, 20)
+        print(json.dumps({"inplace_sphere_f64": {"ms_per_step": round(1e3 * dta / 200, 5),
+                                                 "mlups": round(sp.cells * 200 / dta / 1e6, 1)}}),
+              flush=True)
+        return
     if args.reverse_only:
         print(json.dumps({"adjoint_sphere_f64": {
             k: _round(v) for k, v in bench_adjoint(ri.sphere(), 60, 5).items()}}), flush=True)
