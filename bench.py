@@ -61,7 +61,8 @@ def counted_traffic(launch_seconds: float):
 def algorithmic_bytes(s, elem: int, with_f: bool = True) -> dict:
     """Bytes one step must move: every updated (non-solid, non-inflow) cell reads
     and writes 19 values per population; inflow cells write them only; each cell
-    reads its 1-byte class when an obstacle mask is present."""
+    reads its 4-byte cell word (solid, near and bounce bits) when an obstacle
+    mask is present."""
     cells = s.cells
     solid = 0 if s.solid is None else int(s.solid.sum())
     inflow = 0
@@ -80,7 +81,7 @@ def algorithmic_bytes(s, elem: int, with_f: bool = True) -> dict:
     upd = cells - solid - inflow
     pops = 2 if with_f else 1
     per_upd = pops * Q * 2 * elem
-    b = upd * per_upd + inflow * pops * Q * elem + (cells if s.solid is not None else 0)
+    b = upd * per_upd + inflow * pops * Q * elem + (4 * cells if s.solid is not None else 0)
     return {"bytes": b, "updated_cells": upd, "inflow_cells": inflow, "solid_cells": solid,
             "bytes_per_updated_cell": per_upd}
 

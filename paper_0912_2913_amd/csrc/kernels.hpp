@@ -36,8 +36,12 @@
 namespace rlb {
 
 constexpr int BLOCK = 256;
-constexpr uint8_t CLS_SOLID = 1;
-constexpr uint8_t CLS_NEAR = 2;  // some resolved neighbour is solid
+// Cell word (one uint32 per cell, when an obstacle exists): bit 0 solid,
+// bit 1 near (some resolved neighbour is solid), bit CLS_BOUNCE + q set when
+// the resolved pull source of direction q is solid (half-way bounce-back).
+constexpr uint32_t CLS_SOLID = 1u;
+constexpr uint32_t CLS_NEAR = 2u;
+constexpr int CLS_BOUNCE = 8;
 
 // Division by a runtime constant via multiply-high (valid for n < 2^31).
 struct FastDiv {
@@ -96,7 +100,7 @@ struct Phys {
   double eos_A, eos_B, eos_C, eos_H, eos_F, eos_G;  // inversion constants (see invert)
   double n_ref, e_ref;          // zero unless the storage holds deviations
   const double *omega;          // [batch] 1/tau
-  const uint8_t *cls;           // [cells] class bits, or null (no obstacle)
+  const uint32_t *cls;          // [cells] cell words, or null (no obstacle)
   const double *omega_cell;     // [cells] 1/tau(x) of a per-cell tau field, or null
   double *dtau_cell;            // [cells] reverse-sweep dL/dtau(x) accumulator, or null
   double eta_s, d_G;            // eta_s > 0: tau from the local state holds eta/s
@@ -419,37 +423,37 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *out) {
 }
 
 // Element offset of the pull of direction q for cell c: the resolved source
-// (wrap / clamp by the branch-free face corrections), or, for a cell next to
-// a solid (near) whose source is solid, its own opposite population
-// (half-way bounce-back).  Both candidates have compile-time directions after
-// unrolling; only near lanes read the source's class byte.
-__device__ __forceinline__ size_t pull_at(const Geom &g, const Phys &ph, const Cell &c,
-                                          const FaceCorr &fc, bool near, int q) {
-  const long long s = src_fast(g, c, fc, q);
-  if (near && (ph.cls[s] & CLS_SOLID)) return at(OPP[q], c.idx);
-  return at(q, s);
+// (wrap / clamp by the branch-free face corrections), or, when the cell word
+// `cls` (0 without an obstacle) marks that source solid, the cell's own
+// opposite population (half-way bounce-back).  Both candidates have
+// compile-time directions after unrolling, and the choice needs no load
+// beyond the cell's own word.
+__device__ __forceinline__ size_t pull_at(const Geom &g, const Cell &c, const FaceCorr &fc,
+                                          uint32_t cls, int q) {
+  if ((cls >> (CLS_BOUNCE + q)) & 1u) return at(OPP[q], c.idx);
+  return at(q, src_fast(g, c, fc, q));
 }
 
 // Pull the 19 values of one population for cell c (decoded to the compute type).
 template <class Cd>
-__device__ __forceinline__ void gather(const Geom &g, const Phys &ph, const Cell &c, bool near,
+__device__ __forceinline__ void gather(const Geom &g, const Cell &c, uint32_t cls,
                                        const typename Cd::elem *__restrict__ P,
                                        typename Cd::calc (&v)[Q]) {
   const FaceCorr fc = face_corr(g, c);
 #pragma unroll
-  for (int q = 0; q < Q; ++q) v[q] = Cd::dec(P[pull_at(g, ph, c, fc, near, q)]);
+  for (int q = 0; q < Q; ++q) v[q] = Cd::dec(P[pull_at(g, c, fc, cls, q)]);
 }
 
 // Both populations of cell c, pulled in one pass (same sources for f and g).
 template <class Cd>
-__device__ __forceinline__ void gather2(const Geom &g, const Phys &ph, const Cell &c, bool near,
+__device__ __forceinline__ void gather2(const Geom &g, const Cell &c, uint32_t cls,
                                         const typename Cd::elem *__restrict__ G,
                                         const typename Cd::elem *__restrict__ F,
                                         typename Cd::calc (&vg)[Q], typename Cd::calc (&vf)[Q]) {
   const FaceCorr fc = face_corr(g, c);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const size_t o = pull_at(g, ph, c, fc, near, q);
+    const size_t o = pull_at(g, c, fc, cls, q);
     vg[q] = Cd::dec(G[o]);
     vf[q] = Cd::dec(F[o]);
   }
@@ -480,7 +484,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
   using El = typename Cd::elem;
   const Cell c = decode_cell(g);
   if (!c.active) return;
-  const uint8_t cls = (HELD && ph.cls) ? ph.cls[c.idx] : (uint8_t)0;
+  const uint32_t cls = (HELD && ph.cls) ? ph.cls[c.idx] : 0u;
   // Solid cells keep their (zero) entries and inflow-plane cells the inflow
   // equilibrium; both still run the common path (their pulls stay in the
   // domain) so that every lane joins the same full-wavefront stores, with the
@@ -492,12 +496,11 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
   El *__restrict__ gd = DO_F ? dst + Q * qs : dst;
   // All 38 pulls are issued before any arithmetic (both populations in
   // flight per wave); g then f are relaxed and streamed out.
-  const bool near = HELD && (cls & CLS_NEAR);
   T pg[Q], pf[Q];
   if (DO_F)
-    gather2<Cd>(g, ph, c, near, gs, src, pg, pf);
+    gather2<Cd>(g, c, cls, gs, src, pg, pf);
   else
-    gather<Cd>(g, ph, c, near, gs, pg);
+    gather<Cd>(g, c, cls, gs, pg);
   T sE = (T)0, sx, sy, sz;
 #pragma unroll
   for (int q = 0; q < Q; ++q) sE += pg[q];
@@ -915,7 +918,7 @@ __device__ __forceinline__ bool covered(const Geom &g, const Phys &ph, const Cel
 // every other cell (solid, inflow, next to a solid, on an outflow face or next
 // to an inflow plane) goes to the general path, through a precomputed list.
 __device__ __forceinline__ bool adjoint_plain(const Geom &g, const Phys &ph, const Cell &c) {
-  const uint8_t cls = ph.cls ? ph.cls[c.idx] : (uint8_t)0;
+  const uint32_t cls = ph.cls ? ph.cls[c.idx] : 0u;
   return !(cls & (CLS_SOLID | CLS_NEAR)) && !is_inflow(g, c.x, c.y, c.z) &&
          in_fast(c, g.alo, g.ahi);
 }
@@ -1338,19 +1341,23 @@ __global__ __launch_bounds__(BLOCK) void k_init_adjoint(
     for (int k2 = 0; k2 < 5; ++k2) part[(size_t)c.L * 5 + k2] = out[k2];
 }
 
-// Cell classes: solid bit from the caller's mask, "near" bit when any of the
-// 18 resolved neighbours is solid.
+// Cell words: solid bit from the caller's mask; bounce bit q when the
+// resolved pull source of direction q (wrapped or clamped) is solid; "near"
+// when any of the 18 moving directions bounces.
 __global__ __launch_bounds__(BLOCK) void k_classify(const Geom g, const uint8_t *__restrict__ solid,
-                                                    uint8_t *__restrict__ cls) {
+                                                    uint32_t *__restrict__ cls) {
   const Cell c = decode_cell(g);
   if (!c.active) return;
-  uint8_t v = solid[c.idx] ? CLS_SOLID : (uint8_t)0;
-  for (int q = 1; q < Q; ++q) {
+  uint32_t v = solid[c.idx] ? CLS_SOLID : 0u;
+  for (int q = 0; q < Q; ++q) {
     bool cl = false;
     const int sx = resolve(g, 0, c.x - EX[q], cl);
     const int sy = resolve(g, 1, c.y - EY[q], cl);
     const int sz = resolve(g, 2, c.z - EZ[q], cl);
-    if (solid[cell_index(g, c.b, sx, sy, sz)]) v |= CLS_NEAR;
+    if (solid[cell_index(g, c.b, sx, sy, sz)]) {
+      v |= 1u << (CLS_BOUNCE + q);
+      if (q > 0) v |= CLS_NEAR;
+    }
   }
   cls[c.idx] = v;
 }
@@ -1482,7 +1489,7 @@ __global__ __launch_bounds__(BLOCK) void k_aa_swap(const Geom g, const Phys ph, 
 // overwritten by its held values at the next local step, so the layer next
 // to an inflow plane is plain too).
 __device__ __forceinline__ bool aa_plain(const Geom &g, const Phys &ph, const Cell &c) {
-  const uint8_t cls = ph.cls ? ph.cls[c.idx] : (uint8_t)0;
+  const uint32_t cls = ph.cls ? ph.cls[c.idx] : 0u;
   if ((cls & (CLS_SOLID | CLS_NEAR)) || is_inflow(g, c.x, c.y, c.z)) return false;
   const int co[3] = {c.x, c.y, c.z};
   for (int a = 0; a < 3; ++a)

@@ -32,7 +32,7 @@ struct rlb_solver {
   int cur;
   hipStream_t stream;
   double *d_omega;
-  uint8_t *d_cls;
+  uint32_t *d_cls;
   void *d_in_eq;
   unsigned char in_eq_host[2 * Q * 8];  // the same values, read back once at init
   unsigned long long *d_counters;
@@ -755,7 +755,7 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
   if ((e = hipMalloc(&h->d_res, sizeof(double) * 5 * (size_t)p->batch)) != hipSuccess)
     return cleanup_fail(e, "hipMalloc(results)");
   if (solid) {
-    if ((e = hipMalloc(&h->d_cls, (size_t)h->g.qs)) != hipSuccess)
+    if ((e = hipMalloc(&h->d_cls, (size_t)h->g.qs * sizeof(uint32_t))) != hipSuccess)
       return cleanup_fail(e, "hipMalloc(classes)");
     hipLaunchKernelGGL(k_classify, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, solid,
                        h->d_cls);

@@ -18,13 +18,13 @@ def test_sphere_algorithmic_bytes_from_an_independent_count():
     (x-60)^2 + (y-50)^2 + (z-50)^2 <= 15^2, counted here by brute force; the
     x = 0 plane is the inflow plane (no solid on it).  Every other cell reads
     and writes 2 x 19 FP64 values, inflow cells write them only, and every
-    cell reads its 1-byte class."""
+    cell reads its 4-byte cell word."""
     x, y, z = np.meshgrid(np.arange(200), np.arange(100), np.arange(100), indexing="ij")
     solid = int(((x - 60) ** 2 + (y - 50) ** 2 + (z - 50) ** 2 <= 15 ** 2).sum())
     inflow = 100 * 100
     cells = 200 * 100 * 100
     upd = cells - solid - inflow
-    want = upd * 2 * 19 * 2 * 8 + inflow * 2 * 19 * 8 + cells
+    want = upd * 2 * 19 * 2 * 8 + inflow * 2 * 19 * 8 + 4 * cells
     got = bench.algorithmic_bytes(ri.sphere(), 8)
     assert got["solid_cells"] == solid
     assert got["inflow_cells"] == inflow
