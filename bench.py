@@ -165,6 +165,28 @@ def bench_forward(s, steps, warmup):
     return dt, counts
 
 
+def bench_mixed(box_steps=100):
+    """Mixed-precision storage on the 256^3 periodic box (the same step kernel
+    family): time per step, algorithmic GB/s and speed-up over FP64."""
+    import rlb_inputs as ri
+
+    extras = {}
+    t64 = None
+    for st in (ri.F64, ri.F32, ri.F32DEV, ri.F16DEV, ri.BF16DEV):
+        b = ri.periodic_box(storage=st)
+        el = {ri.F64: 8, ri.F32: 4, ri.F32DEV: 4, ri.F16DEV: 2, ri.BF16DEV: 2}[st]
+        dtb, _ = bench_forward(b, box_steps, 5)
+        if st == ri.F64:
+            t64 = dtb
+        gbs = b.cells * 2 * Q * 2 * el / (dtb / box_steps) / 1e9
+        extras[ri.STORAGE_NAMES[st]] = {"mlups": round(b.cells * box_steps / dtb / 1e6, 1),
+                                        "ms_per_step": round(1e3 * dtb / box_steps, 4),
+                                        "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                        "speedup_vs_f64": round(t64 / dtb, 3)}
+        del b
+    return extras
+
+
 def _round(v):
     return round(v, 4) if isinstance(v, float) else v
 
@@ -298,6 +320,9 @@ def main():
     ap.add_argument("--reverse-only", action="store_true",
                     help="only the 60-step FP64 sphere gradient schedule (for kernel traces of "
                          "the reverse step)")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="only the 256^3 box in the five storage formats (for kernel traces of "
+                         "the mixed-precision step)")
     ap.add_argument("--inplace-only", action="store_true",
                     help="only the FP64 sphere with in-place streaming, 200 steps (for kernel "
                          "traces of the in-place kernels)")
@@ -312,6 +337,9 @@ def main():
     import rlb_inputs as ri
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.mixed_only:
+        print(json.dumps({"mixed_precision_256cube": bench_mixed()}), flush=True)
+        return
     if args.inplace_only:
         sp = ri.sphere()
         sp.inplace = True
@@ -365,23 +393,7 @@ def main():
             "steps": 40, "after_warmup": 10, "ms_per_step": round(1e3 * dtp / 40, 5),
             "mlups": round(s.cells * 40 / dtp / 1e6, 2), "unphysical_g_updates": cp[0]}
     if not args.no_extras:
-        extras = {}
-        # mixed-precision storage on the 256^3 periodic box (same step kernel family)
-        box_steps = 100
-        t64 = None
-        for st in (ri.F64, ri.F32, ri.F32DEV, ri.F16DEV, ri.BF16DEV):
-            b = ri.periodic_box(storage=st)
-            el = {ri.F64: 8, ri.F32: 4, ri.F32DEV: 4, ri.F16DEV: 2, ri.BF16DEV: 2}[st]
-            dtb, _ = bench_forward(b, box_steps, 5)
-            if st == ri.F64:
-                t64 = dtb
-            gbs = b.cells * 2 * Q * 2 * el / (dtb / box_steps) / 1e9
-            extras[ri.STORAGE_NAMES[st]] = {"mlups": round(b.cells * box_steps / dtb / 1e6, 1),
-                                            "ms_per_step": round(1e3 * dtb / box_steps, 4),
-                                            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                                            "speedup_vs_f64": round(t64 / dtb, 3)}
-            del b
-        out["mixed_precision_256cube"] = extras
+        out["mixed_precision_256cube"] = bench_mixed()
         # relaxation variants on the FP64 256^3 box: a per-cell tau field (reads
         # 8 more bytes per cell) and tau set per update to hold eta/s (adds the
         # transport arithmetic: a log, a sqrt and divisions per cell)
