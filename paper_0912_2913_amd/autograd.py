@@ -36,6 +36,13 @@ import torch
 from .solver import Solver
 
 
+# Reverse passes of the sqrt(T) schedule overlap each segment's recompute with
+# the previous segment's sweep on lattices of at most this many cells (where a
+# single launch leaves most of the device idle).
+OVERLAP_RECOMPUTE = True
+OVERLAP_MAX_CELLS = 1 << 22
+
+
 def _iroot(T: int, k: int) -> int:
     """Smallest r >= 1 with r**k >= T."""
     r = max(1, int(round(T ** (1.0 / k))))
@@ -139,10 +146,13 @@ class GRun:
         for lv in range(1, len(self.lens)):
             kmax = (self.lens[lv - 1] + self.lens[lv] - 1) // self.lens[lv]
             self._inner.append((sv.new_g(), [sv.new_g() for _ in range(kmax - 1)]))
-        for k in range(self.K - 1, -1, -1):
-            n = min(self.S, self.T - k * self.S)
-            if n > 0:
-                self._reverse(self.ckpt[k], n, 1)
+        if self._overlap():
+            self._reverse_overlapped()
+        else:
+            for k in range(self.K - 1, -1, -1):
+                n = min(self.S, self.T - k * self.S)
+                if n > 0:
+                    self._reverse(self.ckpt[k], n, 1)
         la = self._lam[0]
         self._seq = self._inner = None
         sv.adjoint_flush(dtau, dbin, dein)
@@ -155,6 +165,71 @@ class GRun:
         sv.init_adjoint(la, de0, db0, dbin, dein)
         self._lam = None
         return dtau, dein, dbin, de0, db0, dtc
+
+    def _overlap(self) -> bool:
+        return (OVERLAP_RECOMPUTE and len(self.lens) == 1 and self.K > 1 and self.S > 1
+                and self.sv.cells <= OVERLAP_MAX_CELLS and str(self.sv.device).startswith("cuda"))
+
+    def _reverse_overlapped(self):
+        """The sqrt(T) reverse pass with each segment's recompute overlapped with
+        the previous segment's adjoint sweep: a second solver of the same
+        problem on its own stream (default priority) recomputes segment k-1
+        into one of two sequence buffers while segment k is swept from the
+        other; events order the buffer reuse.  Small lattices leave most of
+        the device idle in each launch, so the two run side by side.  The
+        kernels and their order per buffer are those of the plain pass, so
+        the gradient is the same bit for bit."""
+        sv = self.sv
+        rc = self._helper()
+        s1, s2 = sv.stream, rc.stream
+        s2.wait_stream(s1)  # checkpoints and lambda_T are ready
+        seqs = [self._seq, sv.new_g_seq(self._seq.shape[0])]
+        seqs[1].record_stream(s2)
+        self._seq.record_stream(s2)
+        ready, free = {}, [None, None]
+
+        def recompute(k):
+            n = min(self.S, self.T - k * self.S)
+            buf = seqs[k % 2]
+            if free[k % 2] is not None:
+                s2.wait_event(free[k % 2])
+            if n > 1:
+                rc.step_g(self.ckpt[k], buf[0])
+                rc.trajectory_g(buf, n - 1)
+            ev = torch.cuda.Event()
+            ev.record(s2)
+            ready[k] = ev
+
+        recompute(self.K - 1)
+        for k in range(self.K - 1, -1, -1):
+            if k > 0:
+                recompute(k - 1)
+            s1.wait_event(ready.pop(k))
+            n = min(self.S, self.T - k * self.S)
+            la, lb = self._lam
+            if n > 1:
+                if sv.adjoint_sweep(seqs[k % 2], n - 1, la, lb) is lb:
+                    la, lb = lb, la
+            sv.adjoint_step(self.ckpt[k], la, lb)
+            self._lam = [lb, la]
+            ev = torch.cuda.Event()
+            ev.record(s1)
+            free[k % 2] = ev
+
+    def _helper(self) -> Solver:
+        """The recompute solver of _reverse_overlapped (built once per run)."""
+        if getattr(self, "_rc", None) is None:
+            sv = self.sv
+            self._rc = Solver(sv.setup, device=str(sv.device),
+                              stream=torch.cuda.Stream(device=sv.device))
+            if sv.tau_cell is not None:
+                self._rc.set_tau_field(sv.tau_cell)
+        return self._rc
+
+    def close(self):
+        if getattr(self, "_rc", None) is not None:
+            self._rc.close()
+            self._rc = None
 
     def _reverse(self, start: torch.Tensor, n: int, lv: int):
         """Adjoint steps down through the n steps that begin at state `start`
@@ -240,6 +315,7 @@ class RLBFunction(torch.autograd.Function):
         outs = []
         for g, d, sh in zip((dtau, dein, dbin, de0, db0, dtc), ctx.devs, ctx.shapes):
             outs.append(None if g is None else g.to(d).reshape(sh))
+        run.close()
         run.sv.close()
         ctx.run = None
         return (*outs, None, None, None)
