@@ -237,6 +237,7 @@ def bench_adjoint(s, T, warmup, reps=4, mode="sqrt"):
     sweep(0)
     t_sw = time_steps(sweep, 0, sv.stream) / (reps * S)
     sv.adjoint_flush()
+    run.close()
     sv.close()
     del sv, run, seq, la, lb
     torch.cuda.empty_cache()
