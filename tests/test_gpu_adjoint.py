@@ -167,6 +167,26 @@ def test_checkpointed_equals_store_all_bitwise():
         assert np.array_equal(x, y) and np.array_equal(x, z) and np.array_equal(x, w)
 
 
+def test_overlapped_recompute_equals_sequential_bitwise():
+    """The sqrt(T) reverse pass with each segment's recompute on a second solver
+    and stream (overlapped with the previous segment's sweep) gives the same
+    gradient bit for bit as the pass that recomputes and sweeps in turn."""
+    import paper_0912_2913_amd.autograd as A
+
+    s = setups()["inflow_outflow_obstacle"]
+    saved = A.OVERLAP_RECOMPUTE
+    try:
+        A.OVERLAP_RECOMPUTE = True
+        r1 = _gpu_gradient(s, 40, 5)
+        A.OVERLAP_RECOMPUTE = False
+        r2 = _gpu_gradient(s, 40, 5)
+    finally:
+        A.OVERLAP_RECOMPUTE = saved
+    assert r1[0] == r2[0]
+    for x, y in zip(r1[1:], r2[1:]):
+        assert np.array_equal(x, y)
+
+
 def test_gradient_matches_central_differences_fp64():
     """tau and e0-direction derivatives vs central FD of GPU FP64 forward runs."""
     from paper_0912_2913_amd.autograd import rlb_run
