@@ -418,6 +418,16 @@ def main():
                            "unphysical_updates": int(cnt[0])}
             del b
         out["relaxation_variants_256cube_f64"] = relax
+        # general equation of state P = kappa e (same kernel, other constants)
+        b = ri.periodic_box(storage=ri.F64)
+        b.kappa = 0.25
+        dtb, cnt = bench_forward(b, box_steps, 5)
+        gbs = b.cells * 2 * Q * 2 * 8 / (dtb / box_steps) / 1e9
+        out["general_eos_256cube_f64"] = {
+            "kappa": 0.25, "ms_per_step": round(1e3 * dtb / box_steps, 4),
+            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "vs_kappa_one_third": round(t64 / dtb, 3), "unphysical_updates": int(cnt[0])}
+        del b
         # gradient of a 60-step sphere run (the flow stays physical that long):
         # reverse sweep per step (recompute + adjoint) against one forward step
         for st in (ri.F64, ri.F32):
