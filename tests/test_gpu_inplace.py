@@ -50,6 +50,16 @@ def test_inplace_matches_oracle(name):
     compare(inplace(CASES[name]()), 30)
 
 
+@pytest.mark.parametrize("kappa,c_l", [(0.25, 1.0), (0.7, 2.0)])
+def test_inplace_general_eos_matches_oracle(kappa, c_l):
+    """P = kappa e with in-place streaming, every boundary kind and an
+    obstacle, against the oracle's two-buffer steps at 1e-12."""
+    s = CASES["inflow_outflow_obstacle"]()
+    s.kappa = kappa
+    s.c_l = c_l
+    compare(inplace(s), 30)
+
+
 def test_inplace_small_sphere_matches_oracle():
     """30 x 20 x 20 sphere set-up (inflow |beta| = 0.5, outflow, obstacle of
     radius 4), 20 steps, against the oracle."""
