@@ -142,3 +142,31 @@ def test_general_eos_checkpointed_gradient_matches_oracle(kappa, c_l):
     assert rel(gb0, G.beta0) <= 1e-10
     assert rel(gbi, G.beta_in) <= 1e-10
     assert rel(gei, np.array([G.e_in])) <= 1e-10
+
+
+def test_general_eos_tau_field_gradient_matches_oracle():
+    """A per-cell tau field with P = kappa e: the checkpointed gradient with
+    respect to tau(x) (and the instance tau) against the oracle's reverse
+    sweep at 1e-10."""
+    from paper_0912_2913_amd.autograd import rlb_run
+
+    s = obstacle_setup(508, 0.3)
+    s.tau_cell = np.random.default_rng(509).uniform(0.6, 1.1, s.cells)
+    steps = 20
+    rng = np.random.default_rng(510)
+    C = s.cells
+    a, t = rng.uniform(0.5, 1.5, C), rng.uniform(0.2, 1.0, C)
+    G = oracle.gradient(problem(s), s.e0, s.beta0, steps, oracle.Loss(a=a, t=t))
+    dev = "cuda:0"
+    tau = torch.tensor(s.tau, device=dev, requires_grad=True)
+    tc = torch.tensor(s.tau_cell, device=dev, requires_grad=True)
+    e, _ = rlb_run(s, steps, tau=tau, tau_cell=tc)
+    m = torch.as_tensor(s.solid == 0, device=dev)
+    at, tt = torch.as_tensor(a, device=dev), torch.as_tensor(t, device=dev)
+    L = ((at * (e - tt) ** 2)[m]).sum()
+    L.backward()
+    assert float(L) == pytest.approx(G.loss, rel=1e-12)
+    gtc = tc.grad.cpu().numpy()
+    assert np.abs(gtc - G.tau_cell).max() <= 1e-10 * np.abs(G.tau_cell).max()
+    gt = tau.grad.cpu().numpy()
+    assert np.abs(gt - G.tau).max() <= 1e-10 * np.abs(G.tau).max()
