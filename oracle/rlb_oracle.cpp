@@ -790,7 +790,7 @@ void ora_update_cells(const int32_t *dims, double c_l, const int32_t *bc, const 
     }
     double tau = rx.tau_cell ? rx.tau_cell[i] : rx.tau[b];
     if (rx.eta_s > 0.0) tau = tau_for_eta_s(pf, pg, L.c_l, rx.eta_s, rx.d_G);
-    collide<double>(pf, pg, tau, L.c_l, true, o, o + Q);
+    collide<double>(pf, pg, tau, L.c_l, true, o, o + Q, L.kappa);
   }
 }
 

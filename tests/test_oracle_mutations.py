@@ -51,6 +51,8 @@ MUTATIONS = {
     "eos_rest_coefficient": ("3.0 * P * (2.0 + cl2)", "3.0 * P * (1.0 + cl2)"),
     "eos_root_sign": ("T W = ((1.0 + kappa) * E + sqrt(disc)) / 2.0;",
                       "T W = ((1.0 + kappa) * E - sqrt(disc)) / 2.0;"),
+    "update_cells_drops_kappa": ("collide<double>(pf, pg, tau, L.c_l, true, o, o + Q, L.kappa);",
+                                 "collide<double>(pf, pg, tau, L.c_l, true, o, o + Q);"),
     "eos_energy_from_W": ("*eps = W / ((1.0 + kappa) * gamma2);",
                           "*eps = W / ((1.0 + kappa) * gamma2 * gamma2);"),
 }

@@ -318,12 +318,17 @@ def test_sound_speed_is_one_over_sqrt3(c_l):
 
 
 # --------------------------------------------------------------------------- step logic
-def test_update_cells_equals_full_step():
+@pytest.mark.parametrize("kappa,c_l", [(1.0 / 3.0, 1.0), (1.0 / 3.0, 2.0), (0.25, 1.0),
+                                        (0.25, 2.0)])
+def test_update_cells_equals_full_step(kappa, c_l):
+    """The sampled-cell step equals the full step for either equation of state
+    (P = e/3 and P = kappa e, eqs. equil2a/equil2b) and lattice speed."""
     s = ri.random_state_setup(
-        7, 6, 9, batch=2, seed=8,
+        7, 6, 9, batch=2, seed=8, c_l=c_l,
         bc=((ri.INFLOW, ri.OUTFLOW), (ri.PERIODIC, ri.PERIODIC), (ri.OUTFLOW, ri.OUTFLOW)),
         inflow=(1.0, 1.0, 0.1, 0.0, 0.0), solid_centre=(3, 3, 4), solid_radius=1.5)
-    p = problem(s)
+    p = oracle.Problem(s.nx, s.ny, s.nz, s.batch, s.c_l, s.bc, s.inflow, s.tau, s.solid,
+                       kappa=kappa)
     S = oracle.init(p, s.n0, s.e0, s.beta0)
     S1 = S.copy()
     oracle.run(p, S1, 1)
