@@ -176,6 +176,25 @@ rlb_status rlb_current(rlb_solver *h, void **state);
  * RLB_EINVAL after an odd number of steps (S_t is not stored then). */
 rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double *sums);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * fields of rlb_moments, and the same conservation sums, bit for bit, but
+ * written to sums = device double [batch][5] (or NULL) on the solver's
+ * stream, without synchronising and without allocating anything.  The
+ * per-workgroup partials of the sums live in a static device workspace of
+ * 8 MiB that the library holds on every device it runs on until the process
+ * ends (its address is looked up once per device by rlb_init): at most
+ * 8 MiB / 40 B = 209715 workgroups of 256 cells, each instance's cells
+ * rounded up to whole workgroups (about 53.6 million cells in one
+ * instance).  Larger lattices with sums != NULL return RLB_EINVAL with
+ * nothing launched.  Every call on one device shares that workspace:
+ * calls whose work overlaps on one device (several streams, several
+ * threads) race; calls ordered on one stream do not.  Each call rewrites
+ * every partial it reads, so nothing needs clearing between calls.
+ * n, e, beta: as rlb_moments (device double, any may be NULL).  In-place
+ * streaming: RLB_EINVAL after an odd number of steps. */
+rlb_status rlb_moments_noalloc(rlb_solver *h, double *n, double *e, double *beta, double *sums);
+
 /* Fields e [cells] and beta [3][cells] (device double, either may be NULL)
  * of a g block (any state of the g population, e.g. one from rlb_step_g):
  * the constraints for (e, beta) involve g alone.  Zeros on solid cells. */

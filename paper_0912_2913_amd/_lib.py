@@ -23,7 +23,7 @@ EXPORTS = (
     "rlb_fields_g", "rlb_counters", "rlb_adjoint_step", "rlb_moments_adjoint", "rlb_init_adjoint",
     "rlb_destroy", "rlb_status_string", "rlb_last_error", "rlb_advance_g", "rlb_trajectory_g",
     "rlb_adjoint_sweep", "rlb_adjoint_flush", "rlb_set_tau_field", "rlb_hold_eta_over_s",
-    "rlb_transport", "rlb_adjoint_flush_tau_field",
+    "rlb_transport", "rlb_adjoint_flush_tau_field", "rlb_moments_noalloc",
 )
 
 
@@ -74,6 +74,7 @@ def lib():
     L.rlb_step_g.argtypes = [vp, vp, vp]
     L.rlb_current.argtypes = [vp, ctypes.POINTER(vp)]
     L.rlb_moments.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
+    L.rlb_moments_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.rlb_fields_g.argtypes = [vp, vp, vp, vp]
     L.rlb_counters.argtypes = [vp, i64p]
     L.rlb_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -97,7 +98,8 @@ def lib():
                  "rlb_moments", "rlb_fields_g", "rlb_counters", "rlb_adjoint_step", "rlb_moments_adjoint",
                  "rlb_init_adjoint", "rlb_destroy", "rlb_advance_g", "rlb_trajectory_g",
                  "rlb_adjoint_sweep", "rlb_adjoint_flush", "rlb_set_tau_field",
-                 "rlb_hold_eta_over_s", "rlb_transport", "rlb_adjoint_flush_tau_field"):
+                 "rlb_hold_eta_over_s", "rlb_transport", "rlb_adjoint_flush_tau_field",
+                 "rlb_moments_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,21 @@ constexpr int kGraphSlots = 12;
 constexpr int kSeenSlots = 16;
 
 using namespace rlb;
+
+// Device-resident workspace of the allocation-free entry point
+// (rlb_moments_noalloc): per-workgroup reduction partials, 5 doubles per
+// workgroup.  Every device the library runs on holds its own copy until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (kept in
+// g_scratch_addr), never through the array's name.
+constexpr size_t kStaticScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_addr[kMaxDevices] = {};
+}  // namespace
 
 struct rlb_solver {
   rlb_params p;
@@ -63,6 +79,8 @@ struct rlb_solver {
   FaceMap fm;
   int *d_aalist;              // cells of the in-place general path
   int n_aablk;
+  int device;                 // device current at rlb_init
+  double *d_static;           // that device's copy of `scratch` (its device address)
   // Loops of launches replayed as HIP graphs (one per distinct call signature)
   hipStream_t cap;            // private stream the loops are captured on
   struct GraphEntry {
@@ -322,16 +340,19 @@ rlb_status launch_transport(rlb_solver *h, double *T, double *ent, double *eta, 
   return RLB_OK;
 }
 
+// Fields of the current state and, with part != null, its conservation sums
+// reduced through the per-workgroup partials `part` (5 per workgroup) into
+// res[batch][5] (device).
 template <int ST, class TC>
-rlb_status launch_moments(rlb_solver *h, double *n, double *e, double *beta, bool sums) {
+rlb_status launch_moments(rlb_solver *h, double *n, double *e, double *beta, double *part,
+                          double *res) {
   using El = typename Codec<ST, TC>::elem;
   const El *S = (const El *)h->pop[h->cur];
   hipLaunchKernelGGL((k_moments<ST, TC>), dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g, h->ph,
-                     S, S + (size_t)Q * h->g.qs, n, e, beta, sums ? h->d_part : nullptr,
-                     h->inplace ? 1 : 0);
-  if (sums)
-    hipLaunchKernelGGL(k_finish, dim3(h->p.batch), dim3(BLOCK), 0, h->stream, h->d_part,
-                       h->g.nblk_per, (const double *)nullptr, (const int *)nullptr, h->d_res,
+                     S, S + (size_t)Q * h->g.qs, n, e, beta, part, h->inplace ? 1 : 0);
+  if (part)
+    hipLaunchKernelGGL(k_finish, dim3(h->p.batch), dim3(BLOCK), 0, h->stream, part,
+                       h->g.nblk_per, (const double *)nullptr, (const int *)nullptr, res,
                        (double *)nullptr, (double *)nullptr);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
@@ -638,6 +659,23 @@ void free_solver(rlb_solver *h) {
   delete h;
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept for later calls.
+rlb_status static_scratch(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(RLB_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(RLB_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                   hipGetErrorString(e));
+    g_scratch_addr[dev] = (double *)ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return RLB_OK;
+}
+
 rlb_status check_handle(const rlb_solver *h) {
   if (!h) return fail(RLB_EINVAL, "solver handle is NULL");
   return RLB_OK;
@@ -733,6 +771,11 @@ rlb_status rlb_init(rlb_solver **out, const rlb_params *p, const double *tau,
     return fail(RLB_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
   };
   hipError_t e;
+  if ((e = hipGetDevice(&h->device)) != hipSuccess) return cleanup_fail(e, "hipGetDevice");
+  if ((s = static_scratch(h->device, &h->d_static)) != RLB_OK) {
+    free_solver(h);
+    return s;
+  }
   std::vector<double> om(p->batch);
   for (int b = 0; b < p->batch; ++b) om[b] = 1.0 / tau[b];
   if ((e = hipMalloc(&h->d_omega, sizeof(double) * p->batch)) != hipSuccess)
@@ -819,8 +862,9 @@ rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double
   if (check_handle(h) != RLB_OK) return RLB_EINVAL;
   if (h->inplace && h->aa_phase != 0)
     return fail(RLB_EINVAL, "in-place layout after an odd number of steps: S_t is not stored");
+  double *part = sums ? h->d_part : nullptr;
   auto launch = [&]() -> rlb_status {
-    RLB_DISPATCH(h, launch_moments, h, n, e, beta, sums != nullptr);
+    RLB_DISPATCH(h, launch_moments, h, n, e, beta, part, h->d_res);
   };
   rlb_status s = launch();
   if (s != RLB_OK || !sums) return s;
@@ -828,6 +872,22 @@ rlb_status rlb_moments(rlb_solver *h, double *n, double *e, double *beta, double
                          h->stream));
   RLB_HIP(hipStreamSynchronize(h->stream));
   return RLB_OK;
+}
+
+rlb_status rlb_moments_noalloc(rlb_solver *h, double *n, double *e, double *beta,
+                               double *sums) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->inplace && h->aa_phase != 0)
+    return fail(RLB_EINVAL, "in-place layout after an odd number of steps: S_t is not stored");
+  if (!n && !e && !beta && !sums) return fail(RLB_EINVAL, "no output requested");
+  const size_t need = (size_t)h->g.nblk * 5 * sizeof(double);
+  if (sums && need > kStaticScratchBytes)
+    return fail(RLB_EINVAL, "lattice too large for the static workspace: " +
+                                std::to_string(h->g.nblk) + " workgroups need " +
+                                std::to_string(need) + " bytes, the maximum is " +
+                                std::to_string(kStaticScratchBytes));
+  double *part = sums ? h->d_static : nullptr;
+  RLB_DISPATCH(h, launch_moments, h, n, e, beta, part, sums);
 }
 
 rlb_status rlb_fields_g(rlb_solver *h, const void *g_state, double *e, double *beta) {

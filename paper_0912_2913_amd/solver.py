@@ -269,6 +269,13 @@ class Solver:
         check(_lib.lib().rlb_moments(self.h, _ptr(n), _ptr(e), _ptr(b), sp), "rlb_moments")
         return (n, e, b, out) if sums else (n, e, b)
 
+    def moments_noalloc(self, n: torch.Tensor, e: torch.Tensor, beta: torch.Tensor,
+                        sums: Optional[torch.Tensor] = None):
+        """rlb_moments_noalloc into caller-provided device float64 tensors n, e
+        [cells], beta [3, cells] and sums [batch, 5] (or None); asynchronous."""
+        check(_lib.lib().rlb_moments_noalloc(self.h, _ptr(n), _ptr(e), _ptr(beta), _ptr(sums)),
+              "rlb_moments_noalloc")
+
     def fields_g(self, g_state: torch.Tensor):
         """(e [cells], beta [3, cells]) device float64 of a g block."""
         e = torch.empty(self.cells, dtype=torch.float64, device=self.device)
