@@ -69,6 +69,8 @@ def lib():
     rxp = ctypes.POINTER(Relax)
     L.ora_run.argtypes = common + [rxp, _dp, ctypes.c_int]
     L.ora_run.restype = ctypes.c_long
+    L.ora_run_tracked.argtypes = common + [rxp, _dp, ctypes.c_int, _u8p, _lp]
+    L.ora_run_tracked.restype = ctypes.c_long
     L.ora_run_g.argtypes = common + [rxp, _dp, ctypes.c_int]
     L.ora_run_g.restype = ctypes.c_long
     L.ora_update_cells.argtypes = common + [rxp, _dp, ctypes.c_long, _lp, _dp]
@@ -209,6 +211,23 @@ def run(p: Problem, S: np.ndarray, nsteps: int) -> int:
     args, rx = p._args()
     assert S.shape == (2, Q, p.cells) and S.dtype == np.float64 and S.flags.c_contiguous
     return int(lib().ora_run(*args, rx, _d(S), int(nsteps)))
+
+
+def run_tracked(p: Problem, S: np.ndarray, nsteps: int, mark: Optional[np.ndarray] = None):
+    """run() with a record of f-positivity (the discussion section's bound
+    c_i.u > -c_l^2/3 for f^eq_i > 0).  Returns (unphysical updates, updates
+    whose f^eq broke the bound, mark): mark[cells] = 1 where the final f
+    depends on such an update (the update itself or, through the pulls, an
+    earlier one upstream).  Pass the mark of an earlier run to continue it."""
+    if p.eta_s > 0 and p.kappa != 1.0 / 3.0:
+        raise ValueError("the eta/s rule is defined for e = 3P matter (kappa = 1/3)")
+    args, rx = p._args()
+    assert S.shape == (2, Q, p.cells) and S.dtype == np.float64 and S.flags.c_contiguous
+    m = np.zeros(p.cells, np.uint8) if mark is None else np.ascontiguousarray(mark, np.uint8).copy()
+    lost = ctypes.c_long(0)
+    bad = lib().ora_run_tracked(*args, rx, _d(S), int(nsteps), m.ctypes.data_as(_u8p),
+                                ctypes.byref(lost))
+    return int(bad), int(lost.value), m.astype(bool)
 
 
 def run_g(p: Problem, Sg: np.ndarray, nsteps: int) -> int:

@@ -343,12 +343,35 @@ Source pull_source(const Lattice &L, const uint8_t *solid, int b, const int c[3]
   return {si, q};
 }
 
+// Positivity of f^eq (discussion section): every f^eq_i = w_i n gamma
+// (1 + 3 c_i.u / c_l^2) is positive only while c_i.u > -c_l^2/3 for every i.
+// Returns false when some direction breaks that bound (or u is NaN).
+bool feq_positive(const double beta[3], double c_l) {
+  const double cl2 = c_l * c_l;
+  for (int q = 0; q < Q; ++q) {
+    const double cu = c_l * EV[q][0] * beta[0] + c_l * EV[q][1] * beta[1] + c_l * EV[q][2] * beta[2];
+    if (!(1.0 + 3.0 * cu / cl2 > 0.0)) return false;
+  }
+  return true;
+}
+
+// Optional record of a run's f-positivity: `lost` counts the updates whose
+// f^eq broke the bound above; per cell, `mark` is set once the cell's f has
+// depended on such an update (the update itself, or a pull from a marked
+// source: the loss travels with the populations, bounce-back included).
+// Held cells (inflow, solid) are never marked.
+struct PosTrack {
+  std::vector<uint8_t> mark, next;
+  long lost = 0;
+};
+
 // One full time step S_in -> S_out.  Layout S[pop][q][cell], pop 0 = f, 1 = g
 // (cells = batch * nz * ny * nx, x fastest).  With do_f false only the g block
 // is read and written (the pointers then address a g block of 19*cells).
+// trk (f+g FP64 runs only) records f-positivity.
 template <class T>
 long step(const Lattice &L, const Relax<T> &rx, const uint8_t *solid, const T in_f[Q],
-          const T in_g[Q], const T *Sin, T *Sout, bool do_f) {
+          const T in_g[Q], const T *Sin, T *Sout, bool do_f, PosTrack *trk = nullptr) {
   const long C = L.cells();
   const T *fin = Sin, *gin = do_f ? Sin + (long)Q * C : Sin;
   T *fout = Sout, *gout = do_f ? Sout + (long)Q * C : Sout;
@@ -364,6 +387,7 @@ long step(const Lattice &L, const Relax<T> &rx, const uint8_t *solid, const T in
               gout[(long)q * C + i] = 0.0;
               if (do_f) fout[(long)q * C + i] = 0.0;
             }
+            if (trk) trk->next[i] = 0;
             continue;
           }
           if (L.inflow(c)) {
@@ -371,22 +395,38 @@ long step(const Lattice &L, const Relax<T> &rx, const uint8_t *solid, const T in
               gout[(long)q * C + i] = in_g[q];
               if (do_f) fout[(long)q * C + i] = in_f[q];
             }
+            if (trk) trk->next[i] = 0;
             continue;
           }
           T pf[Q], pg[Q], of[Q], og[Q];
+          bool marked = false;
           for (int q = 0; q < Q; ++q) {
             Source s = pull_source(L, solid, b, c, q);
             pg[q] = gin[(long)s.q * C + s.idx];
             pf[q] = do_f ? fin[(long)s.q * C + s.idx] : T(0.0);
+            if (trk && trk->mark[s.idx]) marked = true;
           }
           T tau = rx.tau_cell ? rx.tau_cell[i] : rx.tau[b];
           if (rx.eta_s > 0.0) tau = tau_for_eta_s(pf, pg, L.c_l, rx.eta_s, rx.d_G);
           if (!collide(pf, pg, tau, L.c_l, do_f, of, og, L.kappa)) ++unphysical;
+          if (trk) {
+            // u of this update, as the collision obtained it
+            T N, E, M[3], n, eps, beta[3];
+            moment_sums(pf, pg, L.c_l, &N, &E, M);
+            inv_any(N, E, M, L.kappa, &n, &eps, beta);
+            const double u[3] = {re(beta[0]), re(beta[1]), re(beta[2])};
+            if (!feq_positive(u, L.c_l)) {
+              ++trk->lost;
+              marked = true;
+            }
+            trk->next[i] = marked ? 1 : 0;
+          }
           for (int q = 0; q < Q; ++q) {
             gout[(long)q * C + i] = og[q];
             if (do_f) fout[(long)q * C + i] = of[q];
           }
         }
+  if (trk) std::swap(trk->mark, trk->next);
   return unphysical;
 }
 
@@ -724,6 +764,37 @@ long ora_run(const int32_t *dims, double c_l, const int32_t *bc, const double *i
     std::swap(a, b);
   }
   if (a != S) std::memcpy(S, a, n * sizeof(double));
+  return bad;
+}
+
+// ora_run with a record of f-positivity (see PosTrack): *lost = updates whose
+// f^eq broke the bound c_i.u > -c_l^2/3; mark[cells] = 1 where the final f
+// depends on such an update.  mark may hold an earlier run's record (it is
+// carried on), or zeros.
+long ora_run_tracked(const int32_t *dims, double c_l, const int32_t *bc, const double *inflow,
+                     const uint8_t *solid, const OraRelax *rxp, double *S, int nsteps,
+                     uint8_t *mark, long *lost) {
+  const Relax<double> rx = relax_of(rxp);
+  Lattice L = make_lattice(dims, c_l, bc);
+  L.kappa = kappa_of(rxp->kappa);
+  if (rx.eta_s > 0.0 && !radiation(L.kappa)) return -1;
+  double in_f[Q], in_g[Q];
+  inflow_equilibria<double>(L, inflow[0], inflow[1], inflow + 2, in_f, in_g);
+  const long C = L.cells();
+  const long n = 2L * Q * C;
+  std::vector<double> tmp(n);
+  PosTrack trk;
+  trk.mark.assign(mark, mark + C);
+  trk.next.assign(C, 0);
+  double *a = S, *b = tmp.data();
+  long bad = 0;
+  for (int t = 0; t < nsteps; ++t) {
+    bad += step<double>(L, rx, solid, in_f, in_g, a, b, true, &trk);
+    std::swap(a, b);
+  }
+  if (a != S) std::memcpy(S, a, n * sizeof(double));
+  std::memcpy(mark, trk.mark.data(), C);
+  *lost = trk.lost;
   return bad;
 }
 

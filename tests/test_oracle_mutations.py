@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "rlb_oracle.cpp")
 PINS = [os.path.join(ROOT, "tests", f) for f in
         ("test_oracle_pins.py", "test_oracle_riemann.py", "test_oracle_gradients.py",
-         "test_oracle_transport.py", "test_oracle_eos.py")]
+         "test_oracle_transport.py", "test_oracle_eos.py", "test_oracle_positivity.py")]
 
 MUTATIONS = {
     "drop_quadratic_term": ("6.0 * cu * cu / (cl2 * cl2)", "0.0 * cu * cu / (cl2 * cl2)"),
@@ -51,6 +51,10 @@ MUTATIONS = {
     "eos_rest_coefficient": ("3.0 * P * (2.0 + cl2)", "3.0 * P * (1.0 + cl2)"),
     "eos_root_sign": ("T W = ((1.0 + kappa) * E + sqrt(disc)) / 2.0;",
                       "T W = ((1.0 + kappa) * E - sqrt(disc)) / 2.0;"),
+    "positivity_mark_not_carried": ("if (trk && trk->mark[s.idx]) marked = true;",
+                                    "if (trk && trk->mark[s.idx] && false) marked = true;"),
+    "positivity_bound_coefficient": ("if (!(1.0 + 3.0 * cu / cl2 > 0.0)) return false;",
+                                     "if (!(1.0 + 2.0 * cu / cl2 > 0.0)) return false;"),
     "update_cells_drops_kappa": ("collide<double>(pf, pg, tau, L.c_l, true, o, o + Q, L.kappa);",
                                  "collide<double>(pf, pg, tau, L.c_l, true, o, o + Q);"),
     "eos_energy_from_W": ("*eps = W / ((1.0 + kappa) * gamma2);",
