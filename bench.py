@@ -324,6 +324,9 @@ def main():
     ap.add_argument("--mixed-only", action="store_true",
                     help="only the 256^3 box in the five storage formats (for kernel traces of "
                          "the mixed-precision step)")
+    ap.add_argument("--tubes-only", action="store_true",
+                    help="only the 64-tube FP32 forward and 2000-step gradient (for kernel "
+                         "traces of the launch-bound reverse step)")
     ap.add_argument("--inplace-only", action="store_true",
                     help="only the FP64 sphere with in-place streaming, 200 steps (for kernel "
                          "traces of the in-place kernels)")
@@ -341,17 +344,25 @@ def main():
     if args.mixed_only:
         print(json.dumps({"mixed_precision_256cube": bench_mixed()}), flush=True)
         return
+    if args.tubes_only:
+        print(json.dumps({"tube_batch_64x2048_f32": bench_tubes()}), flush=True)
+        return
     if args.inplace_only:
         sp = ri.sphere()
         sp.inplace = True
         dta, cnt = bench_forward(sp, 200, 20)
-        print(json.dumps({"inplace_sphere_f64": {"ms_per_step": round(1e3 * dta / 200, 5),
-                                                 "mlups": round(sp.cells * 200 / dta / 1e6, 1)}}),
-              flush=True)
+        rec = {"inplace_sphere_f64": {"ms_per_step": round(1e3 * dta / 200, 5),
+                                      "mlups": round(sp.cells * 200 / dta / 1e6, 1)}}
+        if args.copy_probe:
+            rec["copy_probe_GBs"] = round(copy_probe(), 1)
+        print(json.dumps(rec), flush=True)
         return
     if args.reverse_only:
-        print(json.dumps({"adjoint_sphere_f64": {
-            k: _round(v) for k, v in bench_adjoint(ri.sphere(), 60, 5).items()}}), flush=True)
+        rec = {"adjoint_sphere_f64": {
+            k: _round(v) for k, v in bench_adjoint(ri.sphere(), 60, 5).items()}}
+        if args.copy_probe:
+            rec["copy_probe_GBs"] = round(copy_probe(), 1)
+        print(json.dumps(rec), flush=True)
         return
     s = ri.sphere()
     ab = algorithmic_bytes(s, 8)

@@ -48,7 +48,12 @@
  *    the g-only, reverse-mode and held-eta/s entry points are not available.
  *    Same HBM traffic per step, half the state memory.
  *  - Adjoint buffers ("lambda"): one block in the same brick layout, double
- *    for every storage.
+ *    for every storage.  Natural form: lambda(x)_q = dL / dS(x)_q.  Reader
+ *    form (see rlb_adjoint_segment): R(r)_q = the contribution of cell r's
+ *    update through its pull of direction q, stored at r; the natural form
+ *    is its gather, lambda(x)_p = R(x + e_p)_p (or R(x)_opp(p) when x's pull
+ *    of opp(p) bounces off a solid) plus R(r)_p of every cell r whose pull
+ *    of p is clamped onto x by an outflow face.
  *  - Device pointers address memory on the solver's device; every call that
  *    launches work is asynchronous on the stream given to rlb_init unless its
  *    comment says it synchronises.  Nothing throws across the ABI.
@@ -208,6 +213,10 @@ rlb_status rlb_fields_g(rlb_solver *h, const void *g_state, double *e, double *b
  * Returns RLB_EUNPHYSICAL when counts[0] > 0. */
 rlb_status rlb_counters(rlb_solver *h, int64_t counts[2]);
 
+/* Flags of rlb_adjoint_segment. */
+#define RLB_LAM_IN_READER 1  /* lam_a holds lambda in reader form             */
+#define RLB_LAM_OUT_READER 2 /* leave the result in reader form (no gather)   */
+
 /* One reverse step of the g population (the transpose of the linearised
  * update of eq. lbe2 with its streaming and boundary rules):
  *   lam_out = (d S_{t+1} / d S_t)^T lam_next,
@@ -223,7 +232,9 @@ rlb_status rlb_counters(rlb_solver *h, int64_t counts[2]);
  * non-NULL the pending partials of this and all earlier unreduced steps are
  * reduced into them (as rlb_adjoint_flush); with all three NULL they stay
  * pending.  Reductions run in a fixed order, so results are bitwise
- * reproducible and independent of how a sweep is split into calls. */
+ * reproducible and independent of how a sweep is split into calls.  The
+ * step's reader form passes through a library-owned lambda block (allocated
+ * on the first call), then is gathered into lam_out. */
 rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *lam_next,
                             void *lam_out, double *dL_dtau, double *dL_dbeta_in,
                             double *dL_de_in);
@@ -231,12 +242,39 @@ rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *la
 /* n (>= 0) reverse steps in one call: for j = n-1 down to 0, one
  * rlb_adjoint_step with g_state_t = block j of g_seq (layout as in
  * rlb_trajectory_g) and all gradient pointers NULL (the contributions stay
- * pending).  lam_a holds the adjoint after the last state on entry; the
- * steps ping-pong between lam_a and lam_b (distinct device double
- * lambda blocks) and *lam_result (host) receives whichever of the
- * two holds lam after block 0 (lam_a when n is even). */
+ * pending).  lam_a holds the (natural) adjoint after the last state on entry;
+ * lam_a and lam_b (distinct device double lambda blocks) are both
+ * overwritten, and *lam_result (host) receives whichever of the two holds
+ * lambda after block 0: lam_b when n is even and n > 0, else lam_a.  Same as
+ * rlb_adjoint_segment with g_first = NULL and flags = 0. */
 rlb_status rlb_adjoint_sweep(rlb_solver *h, const void *g_seq, int64_t seq_stride, int32_t n,
                              void *lam_a, void *lam_b, void **lam_result);
+
+/* n (>= 0) reverse steps over a stretch of g states in one call, with lambda
+ * passed between calls in either form.  State j of the stretch (j = 0 ..
+ * n-1, stepped from n-1 down to 0): with g_first != NULL, state 0 is g_first
+ * and state j >= 1 is block j-1 of g_seq (a checkpoint read in place followed
+ * by its recomputed successors); with g_first = NULL, state j is block j of
+ * g_seq.  lam_a holds lambda after the last state on entry, in reader form
+ * when flags has RLB_LAM_IN_READER, else natural.  Each step reads lambda
+ * (gathering the reader form with shifted reads) and stores its own
+ * contributions aligned, in reader form, into the other of lam_a / lam_b;
+ * with RLB_LAM_OUT_READER the result stays in reader form, else it is
+ * gathered into the natural form.  *lam_result receives the buffer holding
+ * it; both buffers are overwritten.  The parameter contributions stay pending
+ * (rlb_adjoint_flush), exactly as n rlb_adjoint_step calls would leave them,
+ * and a chain of segments in reader form gives the same lambda bit for bit
+ * as step-by-step natural calls.  RLB_EINVAL for n = 0 with
+ * RLB_LAM_OUT_READER and a natural input (a natural lambda has no reader
+ * form).  Calls of n >= 4 replay captured graphs as rlb_advance_g does. */
+rlb_status rlb_adjoint_segment(rlb_solver *h, const void *g_first, const void *g_seq,
+                               int64_t seq_stride, int32_t n, void *lam_a, void *lam_b,
+                               int32_t flags, void **lam_result);
+
+/* Natural lambda (lam_out, overwritten) from its reader form (lam_reader,
+ * unchanged): the gather described at the top of this file; zeros on solid
+ * cells.  Distinct device double lambda blocks. */
+rlb_status rlb_lam_gather(rlb_solver *h, const void *lam_reader, void *lam_out);
 
 /* Reduce the pending reverse-step partials (fixed order) and add them to
  * dL_dtau[batch], dL_dbeta_in[3], dL_de_in[1] (device double, each may be

@@ -13,7 +13,11 @@ Schedule for T steps with segment length S (default ceil(sqrt(T))):
   backward -- lambda_T from the moment map; for each segment from the last:
               recompute its S - 1 later states from its checkpoint (read in
               place, not copied), then run the adjoint steps down through the
-              segment; finally map lambda_0 to the initial fields.
+              segment in one library call; lambda passes from segment to
+              segment in the library's reader form (each reverse step's
+              contributions stored at the cell that made them) and is gathered
+              into its natural form once, before lambda_0 is mapped to the
+              initial fields.
 Peak storage: K checkpoints + S - 1 segment states + 2 lambda buffers.  S = T
 keeps every state (store-all).
 
@@ -137,6 +141,7 @@ class GRun:
         dbin = torch.zeros(3, dtype=torch.float64, device=dev)
         dein = torch.zeros(1, dtype=torch.float64, device=dev)
         self._lam = [sv.new_lam(), sv.new_lam()]
+        self._reader = False  # form of lambda in self._lam[0]
         sv.moments_adjoint(self.final, dLde.contiguous(), dLdb.contiguous(), self._lam[0])
         # the innermost segment's states after its first (which is the
         # checkpoint itself, read in place)
@@ -154,6 +159,9 @@ class GRun:
                 if n > 0:
                     self._reverse(self.ckpt[k], n, 1)
         la = self._lam[0]
+        if self._reader:
+            sv.lam_gather(la, self._lam[1])
+            la = self._lam[1]
         self._seq = self._inner = None
         sv.adjoint_flush(dtau, dbin, dein)
         dtc = None
@@ -206,15 +214,19 @@ class GRun:
                 recompute(k - 1)
             s1.wait_event(ready.pop(k))
             n = min(self.S, self.T - k * self.S)
-            la, lb = self._lam
-            if n > 1:
-                if sv.adjoint_sweep(seqs[k % 2], n - 1, la, lb) is lb:
-                    la, lb = lb, la
-            sv.adjoint_step(self.ckpt[k], la, lb)
-            self._lam = [lb, la]
+            self._segment(self.ckpt[k], seqs[k % 2], n)
             ev = torch.cuda.Event()
             ev.record(s1)
             free[k % 2] = ev
+
+    def _segment(self, start: torch.Tensor, seq: torch.Tensor, n: int):
+        """The n reverse steps of the states (start, seq[0], ..., seq[n-2]) in
+        one library call, lambda kept in reader form."""
+        la, lb = self._lam
+        res = self.sv.adjoint_segment(start, seq if n > 1 else None, n, la, lb,
+                                      in_reader=self._reader, out_reader=True)
+        self._lam = [res, lb if res is la else la]
+        self._reader = True
 
     def _helper(self) -> Solver:
         """The recompute solver of _reverse_overlapped (built once per run)."""
@@ -239,17 +251,13 @@ class GRun:
         innermost level the n states are recomputed and swept."""
         sv = self.sv
         if lv >= len(self.lens):
-            # states start+1 .. start+n-1 into the sequence buffer, their n-1
-            # reverse steps, then the reverse step of `start` read in place
+            # states start+1 .. start+n-1 into the sequence buffer, then the n
+            # reverse steps down to `start`, read in place
             seq = self._seq
-            la, lb = self._lam
             if n > 1:
                 sv.step_g(start, seq[0])
                 sv.trajectory_g(seq, n - 1)
-                if sv.adjoint_sweep(seq, n - 1, la, lb) is lb:
-                    la, lb = lb, la
-            sv.adjoint_step(start, la, lb)
-            self._lam = [lb, la]
+            self._segment(start, seq, n)
             return
         L = self.lens[lv]
         tmp, bufs = self._inner[lv - 1]

@@ -68,7 +68,6 @@ struct Geom {
   // e_a = -1): +-n*stride wraps a periodic axis, +-stride clamps an outflow
   // axis onto the face (zero-gradient copy), 0 on a periodic axis of one cell.
   int corr_lo[3], corr_hi[3];
-  int alo[3], ahi[3];  // adjoint fast range per axis (whole axis if periodic)
 };
 
 // Values the inflow plane holds (f then g, storage format), passed by value
@@ -176,11 +175,6 @@ __device__ __forceinline__ bool is_inflow(const Geom &g, int x, int y, int z) {
   return (g.inflow_lo[0] && x == 0) || (g.inflow_hi[0] && x == g.n[0] - 1) ||
          (g.inflow_lo[1] && y == 0) || (g.inflow_hi[1] && y == g.n[1] - 1) ||
          (g.inflow_lo[2] && z == 0) || (g.inflow_hi[2] && z == g.n[2] - 1);
-}
-
-__device__ __forceinline__ bool in_fast(const Cell &c, const int lo[3], const int hi[3]) {
-  return c.x >= lo[0] && c.x <= hi[0] && c.y >= lo[1] && c.y <= hi[1] && c.z >= lo[2] &&
-         c.z <= hi[2];
 }
 
 // Branch-free pull sources of a cell with no solid neighbour: the per-lane
@@ -377,6 +371,16 @@ __device__ __forceinline__ double rest_g(const Phys &ph, int q) {
 }
 __device__ __forceinline__ double rest_f(const Phys &ph, int q) { return WQ[q] * ph.n_ref; }
 
+// f^eq_i >= 0 needs 1 + 3 b_i > 0 for every i (the discussion section's
+// positivity bound); the largest |b_i| is on a diagonal: |b_x| + |b_y|,
+// |b_x| + |b_z| or |b_y| + |b_z| (over c_l).  True when the bound is broken
+// (or beta is NaN).
+__device__ __forceinline__ bool feq_nonpositive(double bx, double by, double bz, double inv_c) {
+  const double ax = fabs(bx), ay = fabs(by), az = fabs(bz);
+  const double mb = fmax(ax + ay, fmax(ax + az, ay + az)) * inv_c;
+  return !(3.0 * mb < 1.0);
+}
+
 // Event counters: NSLOT slots per counter, one 128-byte line each, picked by
 // workgroup, so that a state where every wave reports (a NaN-filled lattice)
 // does not serialise on one address.  Counter k, slot i lives at
@@ -539,11 +543,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
       const El v = Cd::enc(pf[q] + om * (feq_dev(k, q) - pf[q]));
       stream_store(&dst[at(q, c.idx)], held ? (solid ? zero : in_eq.v[q]) : v);
     }
-    // f^eq_i >= 0 needs 1 + 3 b_i > 0 for every i; the largest |b_i| is on a
-    // diagonal: |b_x| + |b_y|, |b_x| + |b_z| or |b_y| + |b_z|.
-    const double ax = fabs(iv.bx), ay = fabs(iv.by), az = fabs(iv.bz);
-    const double mb = fmax(ax + ay, fmax(ax + az, ay + az)) * ph.inv_c;
-    count_lanes(!(3.0 * mb < 1.0) && !held, counters, 1);
+    count_lanes(feq_nonpositive(iv.bx, iv.by, iv.bz, ph.inv_c) && !held, counters, 1);
   }
 }
 
@@ -883,46 +883,6 @@ __device__ __forceinline__ void eq_param_grad(const Phys &ph, const LamEq &L, do
   out[3] = L.Lbz + t * bz;
 }
 
-// Does some update write lambda_t(x)_p in the main reverse kernel
-// (a streaming reader x + e_p, or x itself by bounce-back)?
-__device__ __forceinline__ bool covered(const Geom &g, const Phys &ph, const Cell &c, int p,
-                                        bool x_inflow) {
-  int r[3] = {c.x + EX[p], c.y + EY[p], c.z + EZ[p]};
-  bool inr = true;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int n = g.n[a];
-    if (g.periodic[a]) {
-      if (r[a] < 0) r[a] += n;
-      if (r[a] >= n) r[a] -= n;
-    } else if (r[a] < 0 || r[a] >= n) {
-      inr = false;
-    }
-  }
-  if (inr) {
-    const long long ri = cell_index(g, c.b, r[0], r[1], r[2]);
-    if (!solid_at(ph, ri) && !is_inflow(g, r[0], r[1], r[2])) return true;
-  }
-  if (!x_inflow) {
-    bool cl = false;
-    const int sx = resolve(g, 0, c.x + EX[p], cl);
-    const int sy = resolve(g, 1, c.y + EY[p], cl);
-    const int sz = resolve(g, 2, c.z + EZ[p], cl);
-    if (solid_at(ph, cell_index(g, c.b, sx, sy, sz))) return true;
-  }
-  return false;
-}
-
-// Which path of the reverse step handles a cell: the streaming path takes cells
-// whose 19 sources and 19 targets are all plain (possibly wrapped) neighbours;
-// every other cell (solid, inflow, next to a solid, on an outflow face or next
-// to an inflow plane) goes to the general path, through a precomputed list.
-__device__ __forceinline__ bool adjoint_plain(const Geom &g, const Phys &ph, const Cell &c) {
-  const uint32_t cls = ph.cls ? ph.cls[c.idx] : 0u;
-  return !(cls & (CLS_SOLID | CLS_NEAR)) && !is_inflow(g, c.x, c.y, c.z) &&
-         in_fast(c, g.alo, g.ahi);
-}
-
 // Cell of a linear index (general paths).
 __device__ __forceinline__ Cell cell_at(const Geom &g, long long idx) {
   Cell c;
@@ -981,174 +941,174 @@ __device__ __forceinline__ double adjoint_mu(const LocalAdjoint &a, double lam, 
   return mu;
 }
 
-// Streaming part of one reverse step of the g population (see
-// rlb_adjoint_step), for a cell where adjoint_plain() holds: pulls pre from
-// S_t, reads lambda_{t+1}(x) and writes mu_q to lambda_t at the source of its
-// pull q; those targets cover every entry of lambda_t that no listed cell
-// writes.  Returns lambda . d post / d tau.
-template <class Cd>
-__device__ __forceinline__ double adjoint_stream_cell(const Geom &g, const Phys &ph, const Cell &c,
-                                                      const typename Cd::elem *__restrict__ S,
-                                                      const LamT *__restrict__ lam_next,
-                                                      LamT *__restrict__ lam_out) {
-  double pre[Q], lam[Q];
-  const FaceCorr fc = face_corr(g, c);
-#pragma unroll
-  for (int q = 0; q < Q; ++q) pre[q] = (double)Cd::dec(S[at(q, src_fast(g, c, fc, q))]);
-#pragma unroll
-  for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, c.idx)];
-  const LocalAdjoint a = adjoint_local(ph, omega_of(ph, c.b, c.idx), pre, lam);
-#pragma unroll
-  for (int q = 0; q < Q; ++q) lam_out[at(q, src_fast(g, c, fc, q))] = adjoint_mu(a, lam[q], q);
-  if (ph.dtau_cell) ph.dtau_cell[c.idx] += a.dtau;
-  return a.dtau;
-}
+// Reverse step in reader form.
+//
+// The transpose of the pull map sends each update's contribution mu_q(r)
+// (from its pull of direction q) to the stored population that pull read.
+// Stored there directly, a wavefront's 64 contributions of one direction land
+// at a shifted address, with a partially written cache line at either end.
+// Instead every update stores its contributions at its own cell, aligned, in
+// the "reader form"
+//     R_t(r)_q = mu_q(r)      (zero for solid and inflow cells: they pull nothing),
+// and lambda_t is gathered from it with the shifted reads of a forward pull:
+//     lambda_t(x)_p = R_t(x)_opp(p)   if x's pull of opp(p) bounces off a solid
+//                   + R_t(x + e_p)_p  otherwise, when x + e_p lies in the domain
+//                   + R_t(r)_p        for every r whose pull of p is clamped onto x.
+// The readers of a clamped pull of p onto x: along each axis k of a clamp
+// pattern m, r_k = x_k with x on the face that e_p points out of (x_k = 0 for
+// e_pk = +1, n - 1 for e_pk = -1); along the other axes r_k = x_k + e_pk.
 
-// Per listed cell of the general reverse path, precomputed once: the 19
-// pull sources (source cell and direction, bounce-back and clamp flags) and
-// the mask of its own lambda_t entries that no update writes.  Layout [Q][n]
-// so that consecutive list entries read consecutive words.
-struct GenTable {
-  const int *src;        // [Q][n] source cell (the cell itself for bounce-back)
-  const uint8_t *srcq;   // [Q][n] source direction | 32 bounce-back | 64 clamped
-  const unsigned *info;  // [n] bit 0 solid, bit 1 inflow, bits 8.. uncovered p
-  int n;
+// Faces of non-periodic axes that a cell lies on.
+struct FaceFlags {
+  bool lo[3], hi[3];
+  bool any;
 };
 
-__global__ __launch_bounds__(BLOCK) void k_adjoint_table(const Geom g, const Phys ph,
-                                                         const int *__restrict__ list, int n,
-                                                         int *__restrict__ src,
-                                                         uint8_t *__restrict__ srcq,
-                                                         unsigned *__restrict__ info) {
-  const int i = (int)(blockIdx.x * BLOCK + threadIdx.x);
-  if (i >= n) return;
-  const int li = list[i];
-  if (li < 0) {
-    info[i] = 0u;
-    for (int q = 0; q < Q; ++q) {
-      src[(size_t)q * n + i] = 0;
-      srcq[(size_t)q * n + i] = 0;
-    }
-    return;
+__device__ __forceinline__ FaceFlags face_flags(const Geom &g, const Cell &c) {
+  FaceFlags f;
+  const int co[3] = {c.x, c.y, c.z};
+  f.any = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    f.lo[a] = !g.periodic[a] && co[a] == 0;
+    f.hi[a] = !g.periodic[a] && co[a] == g.n[a] - 1;
+    f.any = f.any || f.lo[a] || f.hi[a];
   }
-  const Cell c = cell_at(g, li);
-  const bool solid = solid_at(ph, c.idx);
-  const bool inflow = !solid && is_inflow(g, c.x, c.y, c.z);
-  unsigned m = 0u;
-  for (int p = 0; p < Q; ++p)
-    if (solid || !covered(g, ph, c, p, inflow)) m |= 1u << p;
-  info[i] = (solid ? 1u : 0u) | (inflow ? 2u : 0u) | (m << 8);
-  for (int q = 0; q < Q; ++q) {
-    const Pull p = pull_general(g, ph, c, q);
-    src[(size_t)q * n + i] = (int)p.idx;
-    srcq[(size_t)q * n + i] = (uint8_t)(p.q | (p.bounce ? 32 : 0) | (p.clamped ? 64 : 0));
-  }
+  return f;
 }
 
-// General part of the reverse step, for listed cell li = list[i] (see
-// GenTable): zeroes the entries of lambda_t that no update writes, routes an
-// inflow cell's lambda_{t+1} into the inflow gradient (acc[1..4] = de_in,
-// dbeta_in), and scatters through the general pull read from T (bounce-back to
-// the cell's own opposite entry; clamped pulls into `scratch`, indexed by the
-// reading cell, for k_adjoint_faces); acc[0] = lambda . d post / d tau.
-template <class Cd>
-__device__ __forceinline__ void adjoint_general_cell(
-    const Geom &g, const Phys &ph, int li, int i, const GenTable &T,
-    const typename Cd::elem *__restrict__ S, const LamT *__restrict__ lam_next,
-    LamT *__restrict__ lam_out, LamT *__restrict__ scratch, const InflowState &in,
-    double (&acc)[5]) {
-  const unsigned inf = T.info[i];
-  const bool solid = inf & 1u;
-  const bool inflow = inf & 2u;
-  const unsigned unc = inf >> 8;
-  for (int p = 0; p < Q; ++p)
-    if ((unc >> p) & 1u) lam_out[at(p, li)] = 0.0;
-  if (inflow) {
-    double lam[Q];
+// Component a of e_p (compile-time after unrolling).
+__device__ __forceinline__ constexpr int ecomp(int p, int a) {
+  return a == 0 ? EX[p] : (a == 1 ? EY[p] : EZ[p]);
+}
+
+// x + e_p leaves the domain along axis a (through a face of a non-periodic axis).
+__device__ __forceinline__ bool leaves(const FaceFlags &f, int p, int a) {
+  const int e = ecomp(p, a);
+  return (e == 1 && f.hi[a]) || (e == -1 && f.lo[a]);
+}
+
+// A reader of p clamped along axis a onto this cell (the cell is on the face
+// that e_p points out of).
+__device__ __forceinline__ bool clamps_onto(const FaceFlags &f, int p, int a) {
+  const int e = ecomp(p, a);
+  return (e == 1 && f.lo[a]) || (e == -1 && f.hi[a]);
+}
+
+// lambda_t(x)_p gathered from the reader form R (see above).  FACES = false
+// for lattices without non-periodic axes (no clamped reader exists).
+template <bool FACES>
+__device__ __forceinline__ double lam_pull(const Geom &g, const Cell &c, const FaceCorr &fc,
+                                           uint32_t cls, const FaceFlags &ff,
+                                           const LamT *__restrict__ R, int p) {
+  const int q = OPP[p];
+  const bool bounce = (cls >> (CLS_BOUNCE + q)) & 1u;
+  // x + e_p is the source of x's pull of opp(p): its wrap corrections are the
+  // ones src_fast applies
+  const long long plain = src_fast(g, c, fc, q);
+  double v = R[bounce ? at(q, c.idx) : at(p, plain)];
+  if (FACES && ff.any) {
+    if (!bounce && (leaves(ff, p, 0) || leaves(ff, p, 1) || leaves(ff, p, 2))) v = 0.0;
+    const long long stride[3] = {1, (long long)g.n[0], (long long)g.n[0] * g.n[1]};
 #pragma unroll
-    for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, li)];
-    const double g2 = 1.0 / (1.0 - (in.bx * in.bx + in.by * in.by + in.bz * in.bz));
-    const double W = ph.wfac * in.e * g2;
-    const EqCoef<double> k = eq_coef<double>(ph, 0.0, in.e, W, in.bx, in.by, in.bz);
-    const LamEq L = lam_eq(lam_sums(lam, k), ph, W, in.bx, in.by, in.bz);
-    double gr[4];
-    eq_param_grad(ph, L, in.e, in.bx, in.by, in.bz, gr);
-    for (int k2 = 0; k2 < 4; ++k2) acc[1 + k2] = gr[k2];
-  } else if (!solid) {
+    for (int m = 1; m < 8; ++m) {
+      bool possible = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        if (((m >> a) & 1) && ecomp(p, a) == 0) possible = false;
+      if (!possible) continue;  // compile-time after unrolling
+      bool ok = true;
+      long long r = plain;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int e = ecomp(p, a);
+        if (e == 0) continue;
+        if ((m >> a) & 1) {
+          ok = ok && clamps_onto(ff, p, a);
+          r -= e * stride[a];
+        } else {
+          ok = ok && !leaves(ff, p, a);
+        }
+      }
+      if (ok) v += R[at(p, r)];
+    }
+  }
+  return v;
+}
+
+// One reverse step of the g population (see rlb_adjoint_step) in reader form:
+// lambda_{t+1} is read directly (NAT_IN) or gathered from the reader form of
+// the previous reverse step; R_t is stored aligned.  Partials per workgroup,
+// added to the previous step's when accum is set (a reverse sweep accumulates
+// per workgroup in step order, then reduces once): part[L][5] = (dL/dtau,
+// dL/de_in, dL/dbeta_in[3]).  Held cells (solid, inflow) run the common path
+// and store zeros, so that every lane joins the same full-wavefront stores.
+template <int ST, class TC, bool NAT_IN, bool FACES>
+__global__ __launch_bounds__(BLOCK) void k_adjoint(
+    const Geom g, const Phys ph, const typename Codec<ST, TC>::elem *__restrict__ S,
+    const LamT *__restrict__ lam_in, LamT *__restrict__ R_out, double *__restrict__ part,
+    const InflowState in, int accum) {
+  using Cd = Codec<ST, TC>;
+  const Cell c = decode_cell(g);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (c.active) {
+    const uint32_t cls = ph.cls ? ph.cls[c.idx] : 0u;
+    const bool solid = cls & CLS_SOLID;
+    const bool inflow = is_inflow(g, c.x, c.y, c.z);
+    const FaceCorr fc = face_corr(g, c);
+    const FaceFlags ff = face_flags(g, c);
     double pre[Q], lam[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-      pre[q] = (double)Cd::dec(S[at(T.srcq[(size_t)q * T.n + i] & 31, T.src[(size_t)q * T.n + i])]);
+    for (int q = 0; q < Q; ++q) pre[q] = (double)Cd::dec(S[pull_at(g, c, fc, cls, q)]);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) lam[q] = lam_next[at(q, li)];
-    const int b = li / g.per;
-    const LocalAdjoint a = adjoint_local(ph, omega_of(ph, b, li), pre, lam);
-    // Read the table again for the scatter rather than keep the 38 entries
-    // live across the local update (the empty asm hides that the addresses
-    // are the gather's): that keeps this path within the streaming path's
-    // register budget, so that sharing one kernel costs no occupancy.
-    int j = i;
-    asm volatile("" : "+v"(j));
+    for (int p = 0; p < Q; ++p)
+      lam[p] = NAT_IN ? lam_in[at(p, c.idx)] : lam_pull<FACES>(g, c, fc, cls, ff, lam_in, p);
+    if (inflow && !solid) {
+      // the held face: lambda_{t+1} there is the gradient of the inflow state
+      const double g2 = 1.0 / (1.0 - (in.bx * in.bx + in.by * in.by + in.bz * in.bz));
+      const double W = ph.wfac * in.e * g2;
+      const EqCoef<double> k = eq_coef<double>(ph, 0.0, in.e, W, in.bx, in.by, in.bz);
+      const LamEq L = lam_eq(lam_sums(lam, k), ph, W, in.bx, in.by, in.bz);
+      double gr[4];
+      eq_param_grad(ph, L, in.e, in.bx, in.by, in.bz, gr);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const double mu = adjoint_mu(a, lam[q], q);
-      const unsigned fl = T.srcq[(size_t)q * T.n + j];
-      if (fl & 32u)
-        lam_out[at(OPP[q], li)] = mu;
-      else if (fl & 64u)
-        scratch[at(q, li)] = mu;
-      else
-        lam_out[at(q, T.src[(size_t)q * T.n + j])] = mu;
+      for (int k2 = 0; k2 < 4; ++k2) acc[1 + k2] = gr[k2];
     }
-    acc[0] = a.dtau;
-    if (ph.dtau_cell) ph.dtau_cell[li] += a.dtau;
-  }
-}
-
-// One reverse step of the g population (see rlb_adjoint_step) in one launch.
-// The first nlist workgroups (a multiple of 8, so that the others keep their
-// XCD placement) take the listed cells, list[blk * BLOCK + lane] for blk <
-// ngen (-1 = padding; each instance's cells fill whole workgroups), on the
-// general path; the others take the cells where adjoint_plain() holds.  The
-// two sets write disjoint entries of lambda_t, and the listed cells'
-// latency-bound work overlaps the streaming of the rest.  Partials, added to
-// the previous step's when accum is set (a reverse sweep accumulates per
-// workgroup in step order, then reduces once): part[L][5] = (dtau, 0, 0, 0, 0)
-// of streaming workgroup L, part2[blk][5] = (dtau, de_in, dbeta_in[3]) of
-// listed workgroup blk.
-template <int ST, class TC>
-__global__ __launch_bounds__(BLOCK) void k_adjoint(
-    const Geom g, const Phys ph, int nlist, int ngen, const int *__restrict__ list,
-    const GenTable T, const typename Codec<ST, TC>::elem *__restrict__ S,
-    const LamT *__restrict__ lam_next, LamT *__restrict__ lam_out, LamT *__restrict__ scratch,
-    double *__restrict__ part, double *__restrict__ part2, const InflowState in, int accum) {
-  using Cd = Codec<ST, TC>;
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  double *dst;
-  if ((int)blockIdx.x < nlist) {
-    if ((int)blockIdx.x >= ngen) return;
-    const int i = (int)(blockIdx.x * BLOCK + threadIdx.x);
-    const int li = list[i];
-    if (li >= 0) adjoint_general_cell<Cd>(g, ph, li, i, T, S, lam_next, lam_out, scratch, in, acc);
-    dst = part2 + (size_t)blockIdx.x * 5;
-  } else {
-    const Cell c = decode_cell(g, (int)blockIdx.x - nlist);
-    if (c.active && adjoint_plain(g, ph, c))
-      acc[0] = adjoint_stream_cell<Cd>(g, ph, c, S, lam_next, lam_out);
-    dst = part + (size_t)c.L * 5;
+    const bool held = solid || inflow;
+    const LocalAdjoint a = adjoint_local(ph, omega_of(ph, c.b, c.idx), pre, lam);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) R_out[at(q, c.idx)] = held ? 0.0 : adjoint_mu(a, lam[q], q);
+    if (!held) {
+      acc[0] = a.dtau;
+      if (ph.dtau_cell) ph.dtau_cell[c.idx] += a.dtau;
+    }
   }
   double out[5];
   block_sum<5>(acc, out);
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
+    double *dst = part + (size_t)c.L * 5;
+#pragma unroll
     for (int k2 = 0; k2 < 5; ++k2) dst[k2] = (accum ? dst[k2] : 0.0) + out[k2];
+  }
 }
 
-// flag[cell] = 1 for the cells of the general reverse path (host builds the list).
-__global__ __launch_bounds__(BLOCK) void k_mark_general(const Geom g, const Phys ph,
-                                                        uint8_t *__restrict__ flag) {
+// lambda (natural layout) from the reader form: lambda(x)_p as lam_pull
+// gathers it; zeros on solid cells (their populations are never read).
+template <bool FACES>
+__global__ __launch_bounds__(BLOCK) void k_lam_gather(const Geom g, const Phys ph,
+                                                      const LamT *__restrict__ R,
+                                                      LamT *__restrict__ lam) {
   const Cell c = decode_cell(g);
   if (!c.active) return;
-  flag[c.idx] = adjoint_plain(g, ph, c) ? (uint8_t)0 : (uint8_t)1;
+  const uint32_t cls = ph.cls ? ph.cls[c.idx] : 0u;
+  const bool solid = cls & CLS_SOLID;
+  const FaceCorr fc = face_corr(g, c);
+  const FaceFlags ff = face_flags(g, c);
+#pragma unroll
+  for (int p = 0; p < Q; ++p) {
+    const double v = lam_pull<FACES>(g, c, fc, cls, ff, R, p);
+    lam[at(p, c.idx)] = solid ? 0.0 : v;
+  }
 }
 
 // Faces of non-periodic axes, flattened: face f = (axis, side) holds
@@ -1158,111 +1118,6 @@ struct Faces {
   int axis[6], side[6];
   long long start[7];
 };
-
-// Readers whose clamped pulls land on face cells, precomputed once: for
-// face cell t (flattened over the faces) and direction p = 1..18, tgt[t][p-1]
-// = the target cell (-1 when the cell is solid or listed by an earlier face)
-// and rd[t][p-1][m-1], m = 1..7, the reading cell of clamp pattern m (bit k
-// set: clamped along axis k), or -1.  A cell on several faces belongs to the
-// first face that lists it.
-__global__ __launch_bounds__(BLOCK) void k_faces_table(const Geom g, const Phys ph, const Faces F,
-                                                       int *__restrict__ tgt, int *__restrict__ rd) {
-  const long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  if (t >= F.start[F.count]) return;
-  int f = 0;
-  while (t >= F.start[f + 1]) ++f;
-  const int a = F.axis[f];
-  const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;  // the two other axes
-  long long r = t - F.start[f];
-  int co[3];
-  co[u] = (int)(r % g.n[u]);
-  r /= g.n[u];
-  co[v] = (int)(r % g.n[v]);
-  const int b = (int)(r / g.n[v]);
-  co[a] = F.side[f] == 0 ? 0 : g.n[a] - 1;
-  bool skip = false;
-  for (int f2 = 0; f2 < f; ++f2) {
-    const int a2 = F.axis[f2];
-    if (co[a2] == (F.side[f2] == 0 ? 0 : g.n[a2] - 1)) skip = true;
-  }
-  const long long yi = cell_index(g, b, co[0], co[1], co[2]);
-  skip = skip || solid_at(ph, yi);
-  for (int p = 1; p < Q; ++p) {
-    const size_t k = (size_t)t * (Q - 1) + (p - 1);
-    tgt[k] = skip ? -1 : (int)yi;
-    const int e[3] = {EX[p], EY[p], EZ[p]};
-    int nrm[3];
-    bool hn[3], hc[3];
-    for (int d = 0; d < 3; ++d) {
-      const int n = g.n[d];
-      if (e[d] == 0) {
-        nrm[d] = co[d];
-        hn[d] = true;
-        hc[d] = false;
-        continue;
-      }
-      int rr = co[d] + e[d];
-      if (g.periodic[d]) {
-        if (rr < 0) rr += n;
-        if (rr >= n) rr -= n;
-        hn[d] = true;
-      } else {
-        hn[d] = rr >= 0 && rr < n;
-      }
-      nrm[d] = rr;
-      hc[d] = !g.periodic[d] && ((e[d] == 1 && co[d] == 0) || (e[d] == -1 && co[d] == n - 1));
-    }
-    for (int m = 1; m < 8; ++m) {
-      int rc[3];
-      bool ok = !skip;
-      for (int d = 0; d < 3; ++d) {
-        if ((m >> d) & 1) {
-          ok = ok && hc[d];
-          rc[d] = co[d];
-        } else {
-          ok = ok && hn[d];
-          rc[d] = nrm[d];
-        }
-      }
-      int reader = -1;
-      if (ok) {
-        const long long ri = cell_index(g, b, rc[0], rc[1], rc[2]);
-        if (!solid_at(ph, ri) && !is_inflow(g, rc[0], rc[1], rc[2])) reader = (int)ri;
-      }
-      rd[k * 7 + (m - 1)] = reader;
-    }
-  }
-}
-
-// Adds the contributions of clamped pulls (readers on an outflow face whose
-// source was clamped onto the same face) to lambda_t, in a fixed order, from
-// the precomputed reader table: one thread per (face cell, direction).
-template <class Lm>
-__global__ __launch_bounds__(BLOCK) void k_adjoint_faces(long long npairs,
-                                                         const int *__restrict__ tgt,
-                                                         const int *__restrict__ rd,
-                                                         const Lm *__restrict__ scratch,
-                                                         Lm *__restrict__ lam_out) {
-  const long long k = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  if (k >= npairs) return;
-  // the target and the 7 readers are loaded together (one round trip)
-  const int yi = tgt[k];
-  int r[7];
-#pragma unroll
-  for (int m = 0; m < 7; ++m) r[m] = rd[k * 7 + m];
-  if (yi < 0) return;
-  const int p = (int)(k % (Q - 1)) + 1;
-  Lm acc = (Lm)0;
-  bool any = false;
-#pragma unroll
-  for (int m = 0; m < 7; ++m) {
-    if (r[m] >= 0) {
-      acc += scratch[at(p, r[m])];
-      any = true;
-    }
-  }
-  if (any) lam_out[at(p, yi)] += acc;
-}
 
 // lambda_T = (d(e, beta)/d S_T)^T (dL/de, dL/dbeta), cell-local.
 template <int ST, class TC>
@@ -1392,12 +1247,22 @@ __device__ __forceinline__ long long face_pos(const Geom &g, const FaceMap &fm, 
   return fm.start[f] + ((long long)b * g.n[v] + co[v]) * g.n[u] + co[u];
 }
 
+// Event flags of one update: unphysical moments (counter 0) and an f^eq
+// with a non-positive component (counter 1).
+constexpr uint32_t EV_UNPHYSICAL = 1u;
+constexpr uint32_t EV_FNEG = 2u;
+
+__device__ __forceinline__ void count_events(uint32_t ev, unsigned long long *ctr) {
+  count_lanes((ev & EV_UNPHYSICAL) != 0u, ctr, 0);
+  count_lanes((ev & EV_FNEG) != 0u, ctr, 1);
+}
+
 // Relax both populations of one update with the same arithmetic as k_step
 // and hand each post-collision value to sg(q, v) / sf(q, v) as soon as it is
 // formed (g first, then f), so that the pre-collision values die early;
-// returns whether the update was unphysical.
+// returns the update's event flags.
 template <class Cd, class SG, class SF>
-__device__ __forceinline__ bool collide_emit(const Phys &ph, const Cell &c,
+__device__ __forceinline__ uint32_t collide_emit(const Phys &ph, const Cell &c,
                                              const typename Cd::calc (&pg)[Q],
                                              const typename Cd::calc (&pf)[Q], const SG &sg,
                                              const SF &sf) {
@@ -1420,13 +1285,14 @@ __device__ __forceinline__ bool collide_emit(const Phys &ph, const Cell &c,
   k.Nd = (T)(N - ph.n_ref);
 #pragma unroll
   for (int q = 0; q < Q; ++q) sf(q, Cd::enc(pf[q] + om * (feq_dev(k, q) - pf[q])));
-  return iv.bad;
+  return (iv.bad ? EV_UNPHYSICAL : 0u) |
+         (feq_nonpositive(iv.bx, iv.by, iv.bz, ph.inv_c) ? EV_FNEG : 0u);
 }
 
 // Relax both populations of one update in place (pre -> post) with the same
-// arithmetic as k_step; returns whether the update was unphysical.
+// arithmetic as k_step; returns the update's event flags.
 template <class Cd>
-__device__ __forceinline__ bool collide_inplace(const Geom &g, const Phys &ph, const Cell &c,
+__device__ __forceinline__ uint32_t collide_inplace(const Geom &g, const Phys &ph, const Cell &c,
                                                 typename Cd::calc (&pg)[Q],
                                                 typename Cd::calc (&pf)[Q]) {
   using T = typename Cd::calc;
@@ -1448,7 +1314,8 @@ __device__ __forceinline__ bool collide_inplace(const Geom &g, const Phys &ph, c
   k.Nd = (T)(N - ph.n_ref);
 #pragma unroll
   for (int q = 0; q < Q; ++q) pf[q] = pf[q] + om * (feq_dev(k, q) - pf[q]);
-  return iv.bad;
+  return (iv.bad ? EV_UNPHYSICAL : 0u) |
+         (feq_nonpositive(iv.bx, iv.by, iv.bz, ph.inv_c) ? EV_FNEG : 0u);
 }
 
 // Initial state into the in-place layout: a state written in the natural
@@ -1534,7 +1401,7 @@ __global__ __launch_bounds__(BLOCK) void k_aa_local(const Geom g, const Phys ph,
   using T = typename Cd::calc;
   using El = typename Cd::elem;
   const Cell c = decode_cell(g);
-  bool bad = false;
+  uint32_t ev = 0u;
   if (c.active && !solid_at(ph, c.idx)) {
     const size_t qs = (size_t)g.qs;
     El *__restrict__ Af = A;
@@ -1549,17 +1416,16 @@ __global__ __launch_bounds__(BLOCK) void k_aa_local(const Geom g, const Phys ph,
       pf[q] = Cd::dec(Af[at(q, c.idx)]);
       pg[q] = Cd::dec(Ag[at(q, c.idx)]);
     }
-    bad = collide_emit<Cd>(
-              ph, c, pg, pf,
-              [&](int q, El v) { Ag[at(OPP[q], c.idx)] = inflow ? in_eq.v[Q + q] : v; },
-              [&](int q, El v) { Af[at(OPP[q], c.idx)] = inflow ? in_eq.v[q] : v; }) &&
-          !inflow;
+    ev = collide_emit<Cd>(
+        ph, c, pg, pf, [&](int q, El v) { Ag[at(OPP[q], c.idx)] = inflow ? in_eq.v[Q + q] : v; },
+        [&](int q, El v) { Af[at(OPP[q], c.idx)] = inflow ? in_eq.v[q] : v; });
+    if (inflow) ev = 0u;
     // face cells copy what they just stored (same thread: reads see the writes)
     if (face)
       aa_face_copies(g, fm, c, Fb, [&](int q) { return Af[at(OPP[q], c.idx)]; },
                      [&](int q) { return Ag[at(OPP[q], c.idx)]; });
   }
-  count_lanes(bad, counters, 0);
+  count_events(ev, counters);
 }
 
 // f(std::integral_constant<int, q>) for q = 0 .. Q-1, each a separate
@@ -1602,7 +1468,7 @@ __device__ __forceinline__ bool solid_off(unsigned m, int dx, int dy, int dz) {
 // In-place pull step of one updated cell on the general path (listed cells:
 // near a solid, inflow, or on a face of a non-periodic axis).
 template <class Cd>
-__device__ __forceinline__ bool aa_pull_general(const Geom &g, const Phys &ph, const FaceMap &fm,
+__device__ __forceinline__ uint32_t aa_pull_general(const Geom &g, const Phys &ph, const FaceMap &fm,
                                                 typename Cd::elem *__restrict__ A,
                                                 const typename Cd::elem *__restrict__ Fb,
                                                 const HeldEq<typename Cd::elem> &in_eq,
@@ -1615,7 +1481,7 @@ __device__ __forceinline__ bool aa_pull_general(const Geom &g, const Phys &ph, c
   const bool inflow = is_inflow(g, c.x, c.y, c.z);
   const int co[3] = {c.x, c.y, c.z};
   const unsigned sm = solid_around(g, ph, c);
-  bool bad = false;
+  uint32_t ev = 0u;
   T pf[Q], pg[Q];
   if (inflow) {
 #pragma unroll
@@ -1654,7 +1520,7 @@ __device__ __forceinline__ bool aa_pull_general(const Geom &g, const Phys &ph, c
         pg[q] = Cd::dec(Ag[o]);
       }
     }
-    bad = collide_inplace<Cd>(g, ph, c, pg, pf);
+    ev = collide_inplace<Cd>(g, ph, c, pg, pf);
   }
   // one instance of the body per direction (q a constant, so that pf[q] and
   // pg[q] stay in registers and impossible clamp patterns fold away)
@@ -1706,7 +1572,7 @@ __device__ __forceinline__ bool aa_pull_general(const Geom &g, const Phys &ph, c
       Ag[at(OPP[q], c.idx)] = vg;
     }
   });
-  return bad;
+  return ev;
 }
 
 // In-place pull step in one launch: the first nlist workgroups (a multiple
@@ -1725,10 +1591,10 @@ __global__ __launch_bounds__(BLOCK) void k_aa_pull_all(const Geom g, const Phys 
   using Cd = Codec<ST, TC>;
   using T = typename Cd::calc;
   using El = typename Cd::elem;
-  bool bad = false;
+  uint32_t ev = 0u;
   if ((int)blockIdx.x < nlist) {
     const int li = list[(size_t)blockIdx.x * BLOCK + threadIdx.x];
-    if (li >= 0) bad = aa_pull_general<Cd>(g, ph, fm, A, Fb, in_eq, cell_at(g, li));
+    if (li >= 0) ev = aa_pull_general<Cd>(g, ph, fm, A, Fb, in_eq, cell_at(g, li));
   } else {
     const Cell c = decode_cell(g, (int)blockIdx.x - nlist);
     if (c.active && aa_plain(g, ph, c)) {
@@ -1743,12 +1609,12 @@ __global__ __launch_bounds__(BLOCK) void k_aa_pull_all(const Geom g, const Phys 
         pf[q] = Cd::dec(Af[o]);
         pg[q] = Cd::dec(Ag[o]);
       }
-      bad = collide_emit<Cd>(
+      ev = collide_emit<Cd>(
           ph, c, pg, pf, [&](int q, El v) { Ag[at(q, src_fast(g, c, fc, OPP[q]))] = v; },
           [&](int q, El v) { Af[at(q, src_fast(g, c, fc, OPP[q]))] = v; });
     }
   }
-  count_lanes(bad, counters, 0);
+  count_events(ev, counters);
 }
 
 }  // namespace rlb

@@ -56,18 +56,7 @@ struct rlb_solver {
   double *d_part_rev;  // reverse-step partials of the streaming kernel (accumulated)
   double *d_inst;      // [batch][4] per-instance inflow partials
   double *d_res;
-  void *d_scratch;
-  // general-kernel cell list of the reverse step (built on first use)
-  int *d_glist;
-  int *d_gstart;  // [batch + 1] first workgroup of each instance in the list
-  double *d_part2;
-  int *d_gsrc;          // general-cell pull table (see GenTable)
-  uint8_t *d_gsrcq;
-  unsigned *d_ginfo;
-  int *d_ftgt, *d_frd;  // face-reader table (see k_faces_table)
-  int n_gblk;
-  int glist_total;  // list length including padding
-  bool glist_ready;
+  void *d_scratch;   // one lambda block (reader form of single reverse steps)
   bool rev_pending;  // reverse-step partials accumulated and not yet reduced
   bool held;         // solid cells or an inflow plane exist (held cells)
   double *d_omega_cell;       // per-cell 1/tau of a tau field (or null)
@@ -84,10 +73,10 @@ struct rlb_solver {
   // Loops of launches replayed as HIP graphs (one per distinct call signature)
   hipStream_t cap;            // private stream the loops are captured on
   struct GraphEntry {
-    int kind;                 // 0 none, 1 advance, 2 trajectory, 3 sweep
-    const void *a, *b, *c;
+    int kind;                 // 0 none, 1 advance, 2 trajectory, 3 reverse segment
+    const void *a, *b, *c, *d;
     int64_t stride;
-    int n;
+    int n, flags;
     hipGraphExec_t exec;
   } graphs[kGraphSlots], seen[kSeenSlots];  // seen: keys launched once, not captured
   int graph_next, seen_next;
@@ -205,16 +194,11 @@ void setup_geometry(rlb_solver *h) {
     g.inflow_hi[a] = p.bc[a][1] == RLB_BC_INFLOW;
     if (g.inflow_lo[a] || g.inflow_hi[a]) g.any_inflow = 1;
     if (g.periodic[a]) {
-      // wrap: whole axis on the fast paths; one cell: every pull returns to itself
-      g.alo[a] = 0;
-      g.ahi[a] = g.n[a] - 1;
+      // wrap; on an axis of one cell every pull returns to the cell itself
       g.corr_lo[a] = g.n[a] == 1 ? 0 : g.n[a] * stride[a];
       g.corr_hi[a] = g.n[a] == 1 ? 0 : -g.n[a] * stride[a];
     } else {
-      // clamp onto the face; the reverse step keeps face layers (and the layer
-      // next to an inflow plane) on its general path
-      g.alo[a] = 1 + (g.inflow_lo[a] ? 1 : 0);
-      g.ahi[a] = g.n[a] - 2 - (g.inflow_hi[a] ? 1 : 0);
+      // clamp onto the face (zero-gradient copy)
       g.corr_lo[a] = stride[a];
       g.corr_hi[a] = -stride[a];
     }
@@ -397,18 +381,6 @@ rlb_status build_aa_list(rlb_solver *h) {
   return RLB_OK;
 }
 
-// Face-reader table (once per solver): readers whose pulls clamp onto face cells.
-rlb_status build_faces_table(rlb_solver *h) {
-  if (h->faces.count == 0 || h->d_ftgt) return RLB_OK;
-  const long long nf = h->faces.start[h->faces.count];
-  RLB_HIP(hipMalloc(&h->d_ftgt, (size_t)nf * (Q - 1) * sizeof(int)));
-  RLB_HIP(hipMalloc(&h->d_frd, (size_t)nf * (Q - 1) * 7 * sizeof(int)));
-  hipLaunchKernelGGL(k_faces_table, dim3((unsigned)((nf + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
-                     h->stream, h->g, h->ph, h->faces, h->d_ftgt, h->d_frd);
-  RLB_HIP(hipGetLastError());
-  return RLB_OK;
-}
-
 void drop_graphs(rlb_solver *h) {
   for (int i = 0; i < kGraphSlots; ++i)
     if (h->graphs[i].kind) {
@@ -425,10 +397,14 @@ void drop_graphs(rlb_solver *h) {
 // changes them drops the cache.
 template <class F>
 rlb_status run_graph(rlb_solver *h, int kind, const void *a, const void *b, const void *c,
-                     int64_t stride, int n, F body) {
+                     const void *d, int64_t stride, int n, int flags, F body) {
+  auto same = [&](const rlb_solver::GraphEntry &G) {
+    return G.kind == kind && G.a == a && G.b == b && G.c == c && G.d == d &&
+           G.stride == stride && G.n == n && G.flags == flags;
+  };
   for (int i = 0; i < kGraphSlots; ++i) {
     const auto &G = h->graphs[i];
-    if (G.kind == kind && G.a == a && G.b == b && G.c == c && G.stride == stride && G.n == n) {
+    if (same(G)) {
       RLB_HIP(hipGraphLaunch(G.exec, h->stream));
       return RLB_OK;
     }
@@ -436,13 +412,13 @@ rlb_status run_graph(rlb_solver *h, int kind, const void *a, const void *b, cons
   bool seen = false;
   for (int i = 0; i < kSeenSlots && !seen; ++i) {
     auto &K = h->seen[i];
-    if (K.kind == kind && K.a == a && K.b == b && K.c == c && K.stride == stride && K.n == n) {
+    if (same(K)) {
       seen = true;
       K.kind = 0;
     }
   }
   if (!seen) {
-    h->seen[h->seen_next] = {kind, a, b, c, stride, n, nullptr};
+    h->seen[h->seen_next] = {kind, a, b, c, d, stride, n, flags, nullptr};
     h->seen_next = (h->seen_next + 1) % kSeenSlots;
     return body();
   }
@@ -466,79 +442,50 @@ rlb_status run_graph(rlb_solver *h, int kind, const void *a, const void *b, cons
     return fail(RLB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
   auto &G = h->graphs[h->graph_next];
   if (G.kind) (void)hipGraphExecDestroy(G.exec);
-  G = {kind, a, b, c, stride, n, exec};
+  G = {kind, a, b, c, d, stride, n, flags, exec};
   h->graph_next = (h->graph_next + 1) % kGraphSlots;
   RLB_HIP(hipGraphLaunch(exec, h->stream));
   return RLB_OK;
 }
 
-rlb_status build_adjoint_list(rlb_solver *h) {
-  const size_t cells = (size_t)h->g.per * h->p.batch;
-  uint8_t *d_flag = nullptr;
-  RLB_HIP(hipMalloc(&d_flag, cells));
-  hipLaunchKernelGGL(k_mark_general, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
-                     h->ph, d_flag);
-  std::vector<uint8_t> flag(cells);
-  hipError_t e = hipMemcpyAsync(flag.data(), d_flag, cells, hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  (void)hipFree(d_flag);
-  if (e != hipSuccess) return fail(RLB_EDEVICE, std::string("adjoint list: ") + hipGetErrorString(e));
-  std::vector<int> list;
-  std::vector<int> start(h->p.batch + 1, 0);
-  for (int b = 0; b < h->p.batch; ++b) {
-    start[b] = (int)(list.size() / BLOCK);
-    for (int j = 0; j < h->g.per; ++j) {
-      const size_t i = (size_t)b * h->g.per + j;
-      if (flag[i]) list.push_back((int)i);
-    }
-    while (list.size() % BLOCK) list.push_back(-1);
-  }
-  start[h->p.batch] = (int)(list.size() / BLOCK);
-  h->n_gblk = start[h->p.batch];
-  if (h->n_gblk > 0) {
-    RLB_HIP(hipMalloc(&h->d_glist, list.size() * sizeof(int)));
-    RLB_HIP(hipMalloc(&h->d_gstart, start.size() * sizeof(int)));
-    RLB_HIP(hipMalloc(&h->d_part2, (size_t)h->n_gblk * 5 * sizeof(double)));
-    RLB_HIP(hipMemcpy(h->d_glist, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice));
-    RLB_HIP(hipMemcpy(h->d_gstart, start.data(), start.size() * sizeof(int),
-                      hipMemcpyHostToDevice));
-    const size_t n = list.size();
-    RLB_HIP(hipMalloc(&h->d_gsrc, (size_t)Q * n * sizeof(int)));
-    RLB_HIP(hipMalloc(&h->d_gsrcq, (size_t)Q * n));
-    RLB_HIP(hipMalloc(&h->d_ginfo, n * sizeof(unsigned)));
-    hipLaunchKernelGGL(k_adjoint_table, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
-                       h->stream, h->g, h->ph, (const int *)h->d_glist, (int)n, h->d_gsrc,
-                       h->d_gsrcq, h->d_ginfo);
-    RLB_HIP(hipGetLastError());
-  }
-  {
-    rlb_status st = build_faces_table(h);
-    if (st != RLB_OK) return st;
-  }
-  h->glist_total = (int)list.size();
-  h->glist_ready = true;
+// One reverse step into the reader form R_out (see k_adjoint): lambda_{t+1}
+// from lam_in, natural (nat_in) or in reader form.  Its partial sums are added
+// to the pending ones.
+template <int ST, class TC>
+rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_in, bool nat_in,
+                          void *R_out) {
+  using El = typename Codec<ST, TC>::elem;
+  const int accum = h->rev_pending ? 1 : 0;
+  const bool faces = h->faces.count > 0;
+  const dim3 grid(grid_blocks(h)), block(BLOCK);
+  const El *s = (const El *)S;
+  const LamT *li = (const LamT *)lam_in;
+  LamT *ro = (LamT *)R_out;
+  if (nat_in && faces)
+    hipLaunchKernelGGL((k_adjoint<ST, TC, true, true>), grid, block, 0, h->stream, h->g, h->ph, s,
+                       li, ro, h->d_part_rev, h->in, accum);
+  else if (nat_in)
+    hipLaunchKernelGGL((k_adjoint<ST, TC, true, false>), grid, block, 0, h->stream, h->g, h->ph, s,
+                       li, ro, h->d_part_rev, h->in, accum);
+  else if (faces)
+    hipLaunchKernelGGL((k_adjoint<ST, TC, false, true>), grid, block, 0, h->stream, h->g, h->ph, s,
+                       li, ro, h->d_part_rev, h->in, accum);
+  else
+    hipLaunchKernelGGL((k_adjoint<ST, TC, false, false>), grid, block, 0, h->stream, h->g, h->ph,
+                       s, li, ro, h->d_part_rev, h->in, accum);
+  h->rev_pending = true;
+  RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
 
-// One reverse step; its partial sums are added to the pending ones.
-template <int ST, class TC>
-rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_next, void *lam_out) {
-  using El = typename Codec<ST, TC>::elem;
-  const int accum = h->rev_pending ? 1 : 0;
-  // Listed workgroups first, padded to a multiple of the 8 XCDs.
-  const int nlist = (h->n_gblk + 7) / 8 * 8;
-  const GenTable T{h->d_gsrc, h->d_gsrcq, h->d_ginfo, h->glist_total};
-  hipLaunchKernelGGL((k_adjoint<ST, TC>), dim3(nlist + grid_blocks(h)), dim3(BLOCK), 0, h->stream,
-                     h->g, h->ph, nlist, h->n_gblk, (const int *)h->d_glist, T, (const El *)S,
-                     (const LamT *)lam_next, (LamT *)lam_out, (LamT *)h->d_scratch,
-                     h->d_part_rev, h->d_part2, h->in, accum);
-  if (h->faces.count > 0) {
-    const long long npairs = h->faces.start[h->faces.count] * (Q - 1);
-    hipLaunchKernelGGL(k_adjoint_faces<LamT>, dim3((unsigned)((npairs + BLOCK - 1) / BLOCK)),
-                       dim3(BLOCK), 0, h->stream, npairs, (const int *)h->d_ftgt,
-                       (const int *)h->d_frd, (const LamT *)h->d_scratch, (LamT *)lam_out);
-  }
-  h->rev_pending = true;
+// Natural lambda from its reader form.
+rlb_status launch_lam_gather(rlb_solver *h, const void *R, void *lam) {
+  if (h->faces.count > 0)
+    hipLaunchKernelGGL(k_lam_gather<true>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+                       h->ph, (const LamT *)R, (LamT *)lam);
+  else
+    hipLaunchKernelGGL(k_lam_gather<false>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
+                       h->ph, (const LamT *)R, (LamT *)lam);
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
@@ -547,8 +494,8 @@ rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_next, vo
 rlb_status flush_adjoint(rlb_solver *h, double *dtau, double *dbeta_in, double *de_in) {
   if (!h->rev_pending) return RLB_OK;
   hipLaunchKernelGGL(k_finish, dim3(h->p.batch), dim3(BLOCK), 0, h->stream, h->d_part_rev,
-                     h->g.nblk_per, h->n_gblk > 0 ? (const double *)h->d_part2 : nullptr,
-                     (const int *)h->d_gstart, (double *)nullptr, dtau, h->d_inst);
+                     h->g.nblk_per, (const double *)nullptr, (const int *)nullptr,
+                     (double *)nullptr, dtau, h->d_inst);
   if (dbeta_in || de_in)
     hipLaunchKernelGGL(k_finish_inflow, dim3(1), dim3(64), 0, h->stream, (const double *)h->d_inst,
                        h->p.batch, de_in, dbeta_in);
@@ -557,17 +504,12 @@ rlb_status flush_adjoint(rlb_solver *h, double *dtau, double *dbeta_in, double *
   return RLB_OK;
 }
 
-// Start the pending reverse-step partials at zero (kernels only), so that
-// steps may always accumulate.
+// Start the pending reverse-step partials at zero (a kernel, not a memset, so
+// that it may sit in a captured graph), so that steps may always accumulate.
 rlb_status zero_reverse_partials(rlb_solver *h) {
   const long long n1 = 5LL * h->g.nblk;
   hipLaunchKernelGGL(k_zero, dim3((unsigned)((n1 + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, h->stream,
                      h->d_part_rev, n1);
-  if (h->n_gblk > 0) {
-    const long long n2 = 5LL * h->n_gblk;
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n2 + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
-                       h->stream, h->d_part2, n2);
-  }
   h->rev_pending = true;
   RLB_HIP(hipGetLastError());
   return RLB_OK;
@@ -640,14 +582,6 @@ void free_solver(rlb_solver *h) {
   if (h->d_inst) (void)hipFree(h->d_inst);
   if (h->d_res) (void)hipFree(h->d_res);
   if (h->d_scratch) (void)hipFree(h->d_scratch);
-  if (h->d_glist) (void)hipFree(h->d_glist);
-  if (h->d_gstart) (void)hipFree(h->d_gstart);
-  if (h->d_part2) (void)hipFree(h->d_part2);
-  if (h->d_gsrc) (void)hipFree(h->d_gsrc);
-  if (h->d_gsrcq) (void)hipFree(h->d_gsrcq);
-  if (h->d_ginfo) (void)hipFree(h->d_ginfo);
-  if (h->d_ftgt) (void)hipFree(h->d_ftgt);
-  if (h->d_frd) (void)hipFree(h->d_frd);
   if (h->d_omega_cell) (void)hipFree(h->d_omega_cell);
   if (h->d_dtau_cell) (void)hipFree(h->d_dtau_cell);
   if (h->d_bad) (void)hipFree(h->d_bad);
@@ -913,71 +847,90 @@ rlb_status rlb_counters(rlb_solver *h, int64_t counts[2]) {
   return c[0] > 0 ? RLB_EUNPHYSICAL : RLB_OK;
 }
 
-// Lazily allocated reverse-step resources (clamped-pull scratch, general-cell list).
-static rlb_status prepare_adjoint(rlb_solver *h) {
-  if (h->faces.count > 0 && !h->d_scratch)
-    RLB_HIP(hipMalloc(&h->d_scratch, (size_t)Q * h->g.qs * h->lam_elem));
-  if (!h->glist_ready) {
-    rlb_status s = build_adjoint_list(h);
-    if (s != RLB_OK) return s;
-  }
+static rlb_status check_reverse(rlb_solver *h) {
+  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
+  if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
+  if (h->ph.eta_s > 0.0)
+    return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
   return RLB_OK;
 }
 
 rlb_status rlb_adjoint_step(rlb_solver *h, const void *g_state_t, const void *lam_next,
                             void *lam_out, double *dL_dtau, double *dL_dbeta_in,
                             double *dL_de_in) {
-  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
-  if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
-  if (h->ph.eta_s > 0.0)
-    return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
+  rlb_status s = check_reverse(h);
+  if (s != RLB_OK) return s;
   if (!g_state_t || !lam_next || !lam_out || lam_next == lam_out)
     return fail(RLB_EINVAL, "adjoint buffers invalid");
-  rlb_status s = prepare_adjoint(h);
-  if (s != RLB_OK) return s;
+  // the reader form goes to a library-owned block, then is gathered into lam_out
+  if (!h->d_scratch) RLB_HIP(hipMalloc(&h->d_scratch, (size_t)Q * h->g.qs * h->lam_elem));
   auto launch = [&]() -> rlb_status {
-    RLB_DISPATCH(h, launch_adjoint, h, g_state_t, lam_next, lam_out);
+    RLB_DISPATCH(h, launch_adjoint, h, g_state_t, lam_next, true, h->d_scratch);
   };
   s = launch();
+  if (s == RLB_OK) s = launch_lam_gather(h, h->d_scratch, lam_out);
   if (s != RLB_OK) return s;
   if (dL_dtau || dL_dbeta_in || dL_de_in) return flush_adjoint(h, dL_dtau, dL_dbeta_in, dL_de_in);
   return RLB_OK;
 }
 
-rlb_status rlb_adjoint_sweep(rlb_solver *h, const void *g_seq, int64_t seq_stride, int32_t n,
-                             void *lam_a, void *lam_b, void **lam_result) {
-  if (check_handle(h) != RLB_OK) return RLB_EINVAL;
-  if (h->inplace) return fail(RLB_EINVAL, "the g-only and reverse entry points need the two-buffer layout (inplace = 0)");
-  if (h->ph.eta_s > 0.0)
-    return fail(RLB_EINVAL, "g-only steps and reverse steps are unavailable while eta/s is held");
-  if (n < 0 || !lam_a || !lam_b || lam_a == lam_b || !lam_result || (n > 0 && !g_seq) ||
-      seq_stride < 0)
-    return fail(RLB_EINVAL, "adjoint sweep arguments invalid");
-  rlb_status s = prepare_adjoint(h);
+rlb_status rlb_adjoint_segment(rlb_solver *h, const void *g_first, const void *g_seq,
+                               int64_t seq_stride, int32_t n, void *lam_a, void *lam_b,
+                               int32_t flags, void **lam_result) {
+  rlb_status s = check_reverse(h);
   if (s != RLB_OK) return s;
+  const bool in_reader = (flags & RLB_LAM_IN_READER) != 0;
+  const bool out_reader = (flags & RLB_LAM_OUT_READER) != 0;
+  const int blocks = g_first ? n - 1 : n;  // states read from g_seq
+  if (n < 0 || !lam_a || !lam_b || lam_a == lam_b || !lam_result || seq_stride < 0 ||
+      (blocks > 0 && !g_seq) || (flags & ~(RLB_LAM_IN_READER | RLB_LAM_OUT_READER)))
+    return fail(RLB_EINVAL, "adjoint segment arguments invalid");
+  if (n == 0 && out_reader && !in_reader)
+    return fail(RLB_EINVAL, "a natural lambda has no reader form without a reverse step");
+  const int64_t need = (int64_t)Q * h->g.qs * (int64_t)h->elem;
+  if (blocks > 1 && seq_stride < need) return fail(RLB_EINVAL, "seq_stride below one g block");
+  // steps ping-pong between lam_a and lam_b; a final gather (natural output)
+  // writes the buffer not holding the last reader form
+  const int writes = n + ((n > 0 || in_reader) && !out_reader ? 1 : 0);
+  *lam_result = writes % 2 == 0 ? lam_a : lam_b;
   auto body = [&]() -> rlb_status {
     void *cur = lam_a, *nxt = lam_b;
+    bool reader = in_reader;
     for (int j = n - 1; j >= 0; --j) {
-      const void *S = (const char *)g_seq + (size_t)j * (size_t)seq_stride;
+      const void *S = g_first ? (j == 0 ? g_first
+                                        : (const char *)g_seq + (size_t)(j - 1) * (size_t)seq_stride)
+                              : (const char *)g_seq + (size_t)j * (size_t)seq_stride;
       auto launch = [&]() -> rlb_status {
-        RLB_DISPATCH(h, launch_adjoint, h, S, (const void *)cur, nxt);
+        RLB_DISPATCH(h, launch_adjoint, h, S, (const void *)cur, !reader, nxt);
       };
       rlb_status st = launch();
       if (st != RLB_OK) return st;
-      void *t = cur;
-      cur = nxt;
-      nxt = t;
+      std::swap(cur, nxt);
+      reader = true;
     }
+    if (reader && !out_reader) return launch_lam_gather(h, cur, nxt);
     return RLB_OK;
   };
-  *lam_result = n % 2 == 0 ? lam_a : lam_b;
   if (n < kGraphMin) return body();
   // every captured step accumulates onto the pending partials: start them at zero
   if (!h->rev_pending) {
     s = zero_reverse_partials(h);
     if (s != RLB_OK) return s;
   }
-  return run_graph(h, 3, g_seq, lam_a, lam_b, seq_stride, n, body);
+  return run_graph(h, 3, g_seq, lam_a, lam_b, g_first, seq_stride, n, flags, body);
+}
+
+rlb_status rlb_adjoint_sweep(rlb_solver *h, const void *g_seq, int64_t seq_stride, int32_t n,
+                             void *lam_a, void *lam_b, void **lam_result) {
+  return rlb_adjoint_segment(h, nullptr, g_seq, seq_stride, n, lam_a, lam_b, 0, lam_result);
+}
+
+rlb_status rlb_lam_gather(rlb_solver *h, const void *lam_reader, void *lam_out) {
+  rlb_status s = check_reverse(h);
+  if (s != RLB_OK) return s;
+  if (!lam_reader || !lam_out || lam_reader == lam_out)
+    return fail(RLB_EINVAL, "lambda buffers invalid");
+  return launch_lam_gather(h, lam_reader, lam_out);
 }
 
 rlb_status rlb_adjoint_flush(rlb_solver *h, double *dL_dtau, double *dL_dbeta_in,
@@ -1011,7 +964,7 @@ rlb_status rlb_advance_g(rlb_solver *h, const void *g_src, void *g_dst, void *g_
     return RLB_OK;
   };
   if (n < kGraphMin) return body();
-  return run_graph(h, 1, g_src, g_dst, g_tmp, 0, n, body);
+  return run_graph(h, 1, g_src, g_dst, g_tmp, nullptr, 0, n, 0, body);
 }
 
 rlb_status rlb_trajectory_g(rlb_solver *h, void *g_seq, int64_t seq_stride, int32_t n) {
@@ -1032,7 +985,7 @@ rlb_status rlb_trajectory_g(rlb_solver *h, void *g_seq, int64_t seq_stride, int3
     return RLB_OK;
   };
   if (n - 1 < kGraphMin) return body();
-  return run_graph(h, 2, g_seq, nullptr, nullptr, seq_stride, n, body);
+  return run_graph(h, 2, g_seq, nullptr, nullptr, nullptr, seq_stride, n, 0, body);
 }
 
 rlb_status rlb_moments_adjoint(rlb_solver *h, const void *g_state_T, const double *dL_de,

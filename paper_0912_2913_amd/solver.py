@@ -177,6 +177,33 @@ class Solver:
               "rlb_adjoint_sweep")
         return lam_a if res.value == lam_a.data_ptr() else lam_b
 
+    def adjoint_segment(self, g_first: Optional[torch.Tensor], g_seq: Optional[torch.Tensor],
+                        n: int, lam_a: torch.Tensor, lam_b: torch.Tensor,
+                        in_reader: bool = False, out_reader: bool = False) -> torch.Tensor:
+        """n reverse steps over the states (g_first, g_seq[0], ..., g_seq[n-2])
+        (or g_seq[0 .. n-1] without g_first), lambda in lam_a in reader or
+        natural form; returns the buffer (lam_a or lam_b) holding the result
+        (reader form with out_reader)."""
+        blocks = n - 1 if g_first is not None else n
+        if g_seq is not None:
+            if not 0 <= blocks <= g_seq.shape[0]:
+                raise ValueError("n out of range for g_seq")
+            stride = self._seq_stride(g_seq)
+        elif blocks > 0:
+            raise ValueError("g_seq is needed for n > 1")
+        else:
+            stride = 0
+        flags = (_lib.LAM_IN_READER if in_reader else 0) | (_lib.LAM_OUT_READER if out_reader else 0)
+        res = ctypes.c_void_p()
+        check(_lib.lib().rlb_adjoint_segment(self.h, _ptr(g_first), _ptr(g_seq), int(stride), int(n),
+                                             _ptr(lam_a), _ptr(lam_b), int(flags),
+                                             ctypes.byref(res)), "rlb_adjoint_segment")
+        return lam_a if res.value == lam_a.data_ptr() else lam_b
+
+    def lam_gather(self, lam_reader: torch.Tensor, lam_out: torch.Tensor):
+        """Natural lambda from its reader form."""
+        check(_lib.lib().rlb_lam_gather(self.h, _ptr(lam_reader), _ptr(lam_out)), "rlb_lam_gather")
+
     def adjoint_flush(self, dtau=None, dbeta_in=None, de_in=None):
         check(_lib.lib().rlb_adjoint_flush(self.h, _ptr(dtau), _ptr(dbeta_in), _ptr(de_in)),
               "rlb_adjoint_flush")

@@ -284,7 +284,7 @@ def test_adjoint_sweep_equals_pending_adjoint_steps(name):
 
     la, lb = lam_T.clone(), torch.full_like(lam_T, float("nan"))
     res = sv.adjoint_sweep(seq, n, la, lb)
-    assert res is (la if n % 2 == 0 else lb)
+    assert res is (lb if n % 2 == 0 else la)  # n reader-form steps, then the gather
     g_sw = (z(s.batch), z(3), z(1))
     sv.adjoint_flush(*g_sw)
 
@@ -305,6 +305,52 @@ def test_adjoint_sweep_equals_pending_adjoint_steps(name):
     for x, y in zip(g_sw, g_ea):
         x, y = x.cpu().numpy(), y.cpu().numpy()
         assert np.abs(x - y).max() <= 1e-13 * max(np.abs(y).max(), 1e-300)
+    sv.close()
+
+
+@pytest.mark.parametrize("name", ["inflow_outflow_obstacle", "outflow_corners", "tube_batch"])
+def test_reader_form_segments_equal_step_by_step(name):
+    """Segments chained in reader form (a checkpoint read in place plus its
+    successors per call, one gather at the end) give the lambda and the
+    parameter partials of single natural rlb_adjoint_step calls bit for bit."""
+    from paper_0912_2913_amd._lib import RLBError
+    from paper_0912_2913_amd.solver import Solver
+
+    s = setups()[name]
+    sv = Solver(s)
+    T = 9
+    st = sv.new_g_seq(T)
+    st[0].copy_(upload_g(sv, _state_after(s, 2)))
+    sv.trajectory_g(st, T)
+    rng = np.random.default_rng(14)
+    lam_T = upload_lam(sv, rng.standard_normal((19, s.cells)))
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device=sv.device)
+    a, b = lam_T.clone(), sv.new_lam()
+    g_ref = (z(s.batch), z(3), z(1))
+    for j in range(T - 1, -1, -1):
+        sv.adjoint_step(st[j], a, b, *(g_ref if j == 0 else (None, None, None)))
+        a, b = b, a
+    lam_ref = sv.unpack(a)
+    # segments [6, 9), [2, 6), [1, 2), [0, 1): natural in, reader form between
+    la, lb = lam_T.clone(), sv.new_lam()
+    reader = False
+    for lo, hi in ((6, 9), (2, 6), (1, 2), (0, 1)):
+        seq = st[lo + 1:hi].contiguous() if hi - lo > 1 else None
+        res = sv.adjoint_segment(st[lo], seq, hi - lo, la, lb, in_reader=reader, out_reader=True)
+        la, lb = res, (lb if res is la else la)
+        reader = True
+    sv.lam_gather(la, lb)
+    g_seg = (z(s.batch), z(3), z(1))
+    sv.adjoint_flush(*g_seg)
+    assert torch.equal(sv.unpack(lb), lam_ref)
+    for x, y in zip(g_seg, g_ref):
+        assert torch.equal(x, y)
+    # n = 0: a reader-form lambda is gathered; a natural one is returned as is
+    res = sv.adjoint_segment(None, None, 0, la, lb, in_reader=True)
+    assert res is lb
+    assert sv.adjoint_segment(None, None, 0, la, lb) is la
+    with pytest.raises(RLBError):
+        sv.adjoint_segment(None, None, 0, la, lb, out_reader=True)
     sv.close()
 
 
@@ -415,4 +461,68 @@ def test_graph_replays_match_step_by_step_launches():
         assert torch.equal(sv.unpack(res).cpu(), lam_ref), rep
         for x, y in zip(g_sw, g_ref):
             assert torch.equal(x, y), rep
+    sv.close()
+
+
+def decoded_g(sv, s) -> np.ndarray:
+    """The solver's current g block decoded to FP64 [19][cells]: the stored
+    values, plus the rest equilibrium R at (n_ref, e_ref) for the deviation
+    storages (R from the oracle's equilibria at beta = 0); zeros on solid cells."""
+    g = sv.unpack(sv.g_state()).double().cpu().numpy()
+    if s.storage in (ri.F32DEV, ri.F16DEV, ri.BF16DEV):
+        _, R = oracle.equilibria(s.n_ref, s.e_ref, np.zeros(3), s.c_l, s.kappa)
+        g = g + R[:, None]
+    if s.solid is not None:
+        g[:, s.solid.reshape(-1) != 0] = 0.0
+    return np.ascontiguousarray(g)
+
+
+STORAGES = [ri.F32, ri.F32DEV, ri.F16DEV, ri.BF16DEV]
+
+
+@pytest.mark.parametrize("storage", STORAGES, ids=[ri.STORAGE_NAMES[v] for v in STORAGES])
+@pytest.mark.parametrize("name", ["inflow_outflow_obstacle", "outflow_corners", "tachyon"])
+def test_reverse_entry_points_every_storage_match_oracle(name, storage):
+    """The reverse arithmetic is FP64 for every storage: on the GPU's own state
+    (a few forward steps in the storage format), decoded to FP64, the adjoint
+    step, the moment adjoint and the initial-state adjoint match the oracle's
+    complex-step transposes at 1e-12."""
+    from paper_0912_2913_amd.solver import Solver
+
+    s = setups()[name].with_(storage=storage, n_ref=0.9, e_ref=1.05)
+    p = problem(s)
+    sv = Solver(s)
+    sv.step(3)
+    Sg = decoded_g(sv, s)
+    rng = np.random.default_rng(21)
+    lam = rng.standard_normal(Sg.shape)
+    lam_t, dtau, dbin, dein = oracle.adjoint_step(p, Sg, lam)
+    g = sv.g_state().clone()
+    ln = upload_lam(sv, lam)
+    lo = torch.full_like(ln, float("nan"))
+    dt = torch.zeros(s.batch, dtype=torch.float64, device=sv.device)
+    db = torch.zeros(3, dtype=torch.float64, device=sv.device)
+    de = torch.zeros(1, dtype=torch.float64, device=sv.device)
+    sv.adjoint_step(g, ln, lo, dt, db, de)
+    got = sv.unpack(lo).cpu().numpy()
+    assert rel(got, lam_t) <= 1e-12
+    assert rel(dt.cpu().numpy(), dtau) <= 1e-12
+    if any(b == ri.INFLOW for ax in s.bc for b in ax):
+        assert rel(db.cpu().numpy(), dbin) <= 1e-12
+        assert rel(de.cpu().numpy(), np.array([dein])) <= 1e-12
+    dLde = rng.standard_normal(s.cells)
+    dLdb = rng.standard_normal((3, s.cells))
+    lam_ref = oracle.moments_adjoint(p, Sg, dLde, dLdb)
+    lamT = sv.new_lam()
+    sv.moments_adjoint(g, torch.as_tensor(dLde, device=sv.device),
+                       torch.as_tensor(dLdb, device=sv.device), lamT)
+    assert rel(sv.unpack(lamT).cpu().numpy(), lam_ref) <= 1e-12
+    de0_ref, db0_ref, dbin_ref, dein_ref = oracle.init_adjoint(p, s.e0, s.beta0, lam)
+    de0 = torch.empty(s.cells, dtype=torch.float64, device=sv.device)
+    db0 = torch.empty((3, s.cells), dtype=torch.float64, device=sv.device)
+    dbi = torch.zeros(3, dtype=torch.float64, device=sv.device)
+    dei = torch.zeros(1, dtype=torch.float64, device=sv.device)
+    sv.init_adjoint(ln, de0, db0, dbi, dei)
+    assert rel(de0.cpu().numpy(), de0_ref) <= 1e-12
+    assert rel(db0.cpu().numpy(), db0_ref) <= 1e-12
     sv.close()

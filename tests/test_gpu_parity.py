@@ -11,11 +11,19 @@ import torch
 
 import oracle
 import rlb_inputs as ri
-from helpers import field_err, fluid_mask, gpu_state, oracle_fields, problem
+from helpers import field_err, fluid_mask, gpu_state, problem
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
+# Bar for n and f at cells whose f has depended on an update with a
+# non-positive f^eq component (the oracle's record, see oracle.run_tracked):
+# there f grows geometrically and rounding differences are amplified.  Two
+# independent FP64 evaluations of the scheme, the D3Q19 oracle and the lumped
+# D1Q3 one, differ by up to 5.4e-9 of the per-cell rounding scale on the
+# 1 x 1 x 800 tube (tests/test_oracle_positivity.py pins that spread); the bar
+# is 20 times that.
+MARKED_TOL = 1e-7
 
 
 def Solver(s):
@@ -24,10 +32,25 @@ def Solver(s):
     return S(s)
 
 
-def compare(s: ri.Setup, steps: int, tol=TOL, check_n=True):
-    n, e, b, sums, S, bad = oracle_fields(s, steps)
-    sv = Solver(s)
-    sv.step(steps)
+def oracle_tracked(s: ri.Setup, steps: int):
+    """Oracle run with its f-positivity record: (n, e, beta, sums, S, bad, lost, mark)."""
+    p = problem(s)
+    S = oracle.init(p, s.n0, s.e0, s.beta0)
+    bad, lost, mark = oracle.run_tracked(p, S, steps)
+    n, e, b, sums = oracle.moments(p, S)
+    return n, e, b, sums, S, bad, lost, mark
+
+
+def compare_fields(s: ri.Setup, ora, sv, tol=TOL, check_n=True):
+    """GPU solver state against an oracle_tracked() result.
+
+    e and beta (from g alone) and the g populations: norm-wise at tol.  n and f:
+    at tol per cell where the oracle's f never depended on a loss of
+    positivity; elsewhere (only when the oracle counted such updates) at
+    MARKED_TOL of each cell's own rounding scale.  Counters: the GPU's
+    unphysical and non-positive-f^eq counts equal the oracle's.  All five
+    conservation sums, each against its rounding scale."""
+    n, e, b, sums, S, bad, lost, mark = ora
     gn, ge, gb, gsums = [x if isinstance(x, np.ndarray) else x.cpu().numpy()
                          for x in sv.moments(sums=True)]
     m = fluid_mask(s)
@@ -37,29 +60,55 @@ def compare(s: ri.Setup, steps: int, tol=TOL, check_n=True):
     bscale = max(np.abs(b[:, m]).max(), 1e-300)
     for k, ax in enumerate("xyz"):
         errs["beta_" + ax] = float(np.abs(gb[k][m] - b[k][m]).max() / bscale)
-    fin = np.isfinite(n) & m
-    if check_n and fin.any():
-        # n = sqrt(1 - beta^2) sum_i f_i: its rounding scale is sqrt(1 - beta^2) sum_i |f_i|,
-        # which is n itself wherever every f_i >= 0 (the paper's positivity condition)
-        # and far larger where f^eq has negative components and f diverges
-        nscale = np.sqrt(1.0 - (b ** 2).sum(0)) * np.abs(S[0]).sum(0)
-        errs["n"] = float(np.abs(gn[fin] - n[fin]).max() / nscale[fin].max())
     st = gpu_state(sv)
     errs["g_pop"] = field_err(st[1], S[1], m)
     if check_n:
-        finite = np.isfinite(S[0]).all(axis=0) & m
-        errs["f_pop"] = field_err(st[0], S[0], finite)
-    gbad, fbad = sv.counters()
-    # Where f^eq has negative components (c_i.beta < -c_l^2/3, the paper's
-    # positivity bound) f grows geometrically with a rate that depends on beta, so
-    # a 1e-14 difference in beta becomes ~steps x 1e-14 in f and n: those fields
-    # are compared at 1e-10 there; e and beta (from g alone) keep the 1e-12 bar.
-    f_tol = tol if fbad == 0 else 1e-10
+        assert lost > 0 or not mark.any()
+        plain = m & ~mark
+        if plain.any():
+            errs["n_per_cell"] = float((np.abs(gn[plain] - n[plain]) / np.abs(n[plain])).max())
+            errs["f_pop"] = field_err(st[0], S[0], plain)
+        marked = m & mark & np.isfinite(S[0]).all(axis=0)
+        if marked.any():
+            nscale = np.sqrt(1.0 - (b[:, marked] ** 2).sum(0)) * np.abs(S[0][:, marked]).sum(0)
+            fscale = np.abs(S[0][:, marked]).max(0)
+            errs["n_marked"] = float((np.abs(gn[marked] - n[marked]) / nscale).max())
+            errs["f_marked"] = float((np.abs(st[0][:, marked] - S[0][:, marked]) / fscale).max())
     for k, v in errs.items():
-        assert v <= (f_tol if k in ("n", "f_pop") else tol), (k, v, errs)
-    # conservation sums (fixed-order FP64 reductions) against the oracle's
-    assert np.allclose(gsums[:, 1], sums[:, 1], rtol=1e-12, atol=0)
-    assert gbad == bad
+        assert v <= (MARKED_TOL if k.endswith("_marked") else tol), (k, v, errs)
+    gbad, gfbad = sv.counters()
+    assert gbad == bad, (gbad, bad)
+    if check_n:
+        assert gfbad == lost, (gfbad, lost)
+    # Conservation sums (fixed-order FP64 tree reductions on the GPU) against the
+    # same sums of the oracle's populations, summed pairwise (error ~ log2(N)
+    # eps): the oracle's own sums run sequentially over N = 19 * cells terms and
+    # carry up to N eps sum|terms| of rounding (2.9e-4 on the 2M-cell sphere),
+    # which is checked separately.
+    e_int = oracle.lattice()[0].astype(np.float64)  # [19][3]
+    inst = np.arange(s.cells) // (s.cells // s.batch)
+    for bb in range(s.batch):
+        sel = m & (inst == bb)
+        f_b, g_b = S[0][:, sel], S[1][:, sel]
+        terms = [f_b, g_b] + [g_b * (s.c_l * e_int[:, a])[:, None] for a in range(3)]
+        for k, t in enumerate(terms):
+            if k == 0 and not check_n:
+                continue
+            ref = float(np.sum(np.sum(t, axis=0)))
+            scale = float(np.sum(np.abs(t)))
+            if not np.isfinite(ref):
+                continue
+            assert abs(sums[bb, k] - ref) <= t.size * np.finfo(float).eps * scale, (bb, k)
+            k_tol = MARKED_TOL if (k == 0 and lost > 0) else tol
+            assert abs(gsums[bb, k] - ref) <= k_tol * scale, (bb, k, gsums[bb, k], ref, scale)
+    return errs
+
+
+def compare(s: ri.Setup, steps: int, tol=TOL, check_n=True):
+    ora = oracle_tracked(s, steps)
+    sv = Solver(s)
+    sv.step(steps)
+    errs = compare_fields(s, ora, sv, tol, check_n)
     sv.close()
     return errs
 
@@ -114,6 +163,37 @@ def test_shock_tube_full_size():
 def test_paper_pressure_ratio_tube():
     s = ri.shock_tube(e_R=3.2567e-6 / 7.9433e-6, steps=400, tau=0.55)
     compare(s, 400)
+
+
+@pytest.mark.timeout(900)
+def test_sphere_full_field_physical_window(capsys):
+    """The 200 x 100 x 100 sphere over its physical window at c_l = 1 (60 steps,
+    before the flow goes unphysical), every cell against the oracle."""
+    s = ri.sphere()
+    with capsys.disabled():
+        print("\n[parity] sphere 200x100x100: oracle, 60 steps", flush=True)
+    ora = oracle_tracked(s, 60)
+    with capsys.disabled():
+        print(f"[parity] oracle done (lost {ora[6]}); GPU", flush=True)
+    sv = Solver(s)
+    sv.step(60)
+    compare_fields(s, ora, sv)
+    sv.close()
+
+
+@pytest.mark.timeout(900)
+def test_periodic_box_full_field_10_steps(capsys):
+    """The 256^3 periodic box in FP64, 10 steps, every cell against the oracle."""
+    s = ri.periodic_box()
+    with capsys.disabled():
+        print("\n[parity] box 256^3: oracle, 10 steps", flush=True)
+    ora = oracle_tracked(s, 10)
+    with capsys.disabled():
+        print(f"[parity] oracle done (lost {ora[6]}); GPU", flush=True)
+    sv = Solver(s)
+    sv.step(10)
+    compare_fields(s, ora, sv)
+    sv.close()
 
 
 def test_rest_state_exact_and_counters_zero():

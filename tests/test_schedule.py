@@ -73,6 +73,30 @@ class RecurrenceSolver:
             a, b = b, a
         return a
 
+    # The library passes lambda between segments in a "reader form"; the stand-in
+    # models it as the reversed vector, so that a schedule that forgot to
+    # gather it back would fail.
+    def adjoint_segment(self, g_first, g_seq, n, la, lb, in_reader=False, out_reader=False):
+        states = ([g_first] + [g_seq[j] for j in range(n - 1)]) if g_first is not None \
+            else [g_seq[j] for j in range(n)]
+        a, b = la, lb
+        reader = in_reader
+        for x in reversed(states):
+            lam = a.flip(0) if reader else a
+            self.visited.append(x.clone())
+            s = self.A @ x
+            self._pending += (lam * torch.sin(s)).sum()
+            b.copy_((lam + self.h * (self.A.T @ (torch.cos(s) * lam))).flip(0))
+            a, b = b, a
+            reader = True
+        if reader and not out_reader:
+            self.lam_gather(a, b)
+            a, b = b, a
+        return a
+
+    def lam_gather(self, lam_reader, lam_out):
+        lam_out.copy_(lam_reader.flip(0))
+
     def adjoint_flush(self, dtau=None, dbin=None, dein=None):
         if dtau is not None:
             dtau += self._pending
