@@ -191,6 +191,44 @@ def _round(v):
     return round(v, 4) if isinstance(v, float) else v
 
 
+def _fields_after(s, steps):
+    import torch
+
+    from paper_0912_2913_amd.solver import Solver
+
+    sv = Solver(s)
+    sv.step(steps)
+    _, e, b = sv.moments()
+    counts = sv.counters()
+    sv.close()
+    del sv
+    torch.cuda.empty_cache()
+    return e, b, counts
+
+
+def precision_errors(steps=1000):
+    """Errors of the reduced-precision forms on the 256^3 box after `steps`
+    steps against the FP64 run of the same kernel family (max |x - x64| /
+    max |x64| for e and for beta), and their step time."""
+    import rlb_inputs as ri
+
+    e64, b64, _ = _fields_after(ri.periodic_box(), steps)
+    rel = lambda a, b: float((a - b).abs().max() / b.abs().max())
+    out = {}
+    for name, st, col in (("f32", ri.F32, ri.COLLIDE_AUTO), ("f32dev", ri.F32DEV, ri.COLLIDE_AUTO),
+                          ("f32dev_fp32_collide", ri.F32DEV, ri.COLLIDE_F32),
+                          ("f32dev_fp32_collide_fp64_moments", ri.F32DEV, ri.COLLIDE_F32_MOM64),
+                          ("f16dev", ri.F16DEV, ri.COLLIDE_AUTO),
+                          ("bf16dev", ri.BF16DEV, ri.COLLIDE_AUTO)):
+        b = ri.periodic_box(storage=st)
+        b.collide = col
+        e, bt, c = _fields_after(b, steps)
+        dtb, _ = bench_forward(b, 100, 5)
+        out[name] = {"e_err": float("%.3g" % rel(e, e64)), "beta_err": float("%.3g" % rel(bt, b64)),
+                     "ms_per_step": round(1e3 * dtb / 100, 4), "unphysical": int(c[0])}
+    return out
+
+
 def bench_adjoint(s, T, warmup, reps=4, mode="sqrt"):
     """Cost of the gradient of a T-step run with sqrt(T) checkpointing (or the
     3-level schedule), per step, against one forward f+g step: the checkpointed
@@ -280,6 +318,105 @@ def bench_large_gradient(T=4000, modes=("sqrt", "3level")):
     return out
 
 
+def tube_fd_errors(T=2000, h=1e-6):
+    """64-tube workload: the sqrt(T) gradient of sum_b sum_z (e_T - target)^2
+    with respect to tau_b, for FP64, FP32 and FP32-deviation storage, against
+    central FD of FP64 runs (max |g - fd| / max |fd|).  Target: the FP64 final e
+    at (1.02 tau, 1.05 ratio); instances that any of these runs takes
+    unphysical are redrawn from the same seeded stream."""
+    import torch
+
+    import rlb_inputs as ri
+    from paper_0912_2913_amd.autograd import rlb_run
+
+    def tubes(tau, ratio, storage=ri.F64):
+        s = ri.shock_tube(nz=2048, e_L=np.ones(tau.size), e_R=1.0 / ratio, batch=tau.size,
+                          storage=storage)
+        s.tau = np.asarray(tau, dtype=np.float64)
+        return s
+
+    def final_e(s):
+        with torch.no_grad():
+            e, _ = rlb_run(s, T)
+        return e.view(s.batch, -1)
+
+    def reject(tau, ratio):
+        bad = set()
+        for t_, r_ in ((tau, ratio), (1.02 * tau, 1.05 * ratio)):
+            for st in (ri.F64, ri.F32, ri.F32DEV):
+                e = final_e(tubes(t_, r_, st))
+                bad |= set(torch.nonzero(~torch.isfinite(e).all(1) | (e <= 0).any(1))
+                           .flatten().tolist())
+        return bad
+
+    _, tau, ratio, redrawn = ri.tube_batch(reject=reject)
+    target = final_e(tubes(1.02 * tau, 1.05 * ratio))
+    loss = lambda t: ((final_e(tubes(t, ratio)) - target) ** 2).sum(1).cpu().numpy()
+    fd = (loss(tau + h) - loss(tau - h)) / (2 * h)
+    out = {"instances_redrawn": redrawn}
+    for st in (ri.F64, ri.F32, ri.F32DEV):
+        tau_t = torch.tensor(tau, device="cuda", requires_grad=True)
+        e, _ = rlb_run(tubes(tau, ratio, st), T, tau=tau_t)
+        ((e.view(tau.size, -1) - target) ** 2).sum().backward()
+        g = tau_t.grad.cpu().numpy()
+        out["tau_grad_fd_err_" + ri.STORAGE_NAMES[st]] = float("%.3g" % (np.abs(g - fd).max() /
+                                                                          np.abs(fd).max()))
+    return out
+
+
+def large_sphere_steady_gradient(T=4000, h=1e-6):
+    """The 384x192x192 sphere with |beta_in| = 0.3 into fluid at the inflow's
+    energy density (physical over the 4000 steps at c_l = 1): the sqrt(T)
+    gradient of the surface pressure (FP32 storage) with respect to the inflow
+    velocity and tau, its wall time and peak memory, and its agreement with
+    central FD of FP64 runs."""
+    import torch
+
+    import rlb_inputs as ri
+    from paper_0912_2913_amd.autograd import rlb_run, surface_mask
+    from paper_0912_2913_amd.solver import Solver
+
+    s = ri.sphere_large_steady(steps=T, storage=ri.F32)
+    mask = torch.as_tensor(surface_mask(s), device="cuda")
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    t0 = time.perf_counter()
+    bin_t = torch.tensor(s.inflow[2:5], dtype=torch.float64, device="cuda", requires_grad=True)
+    tau_t = torch.tensor(s.tau, device="cuda", requires_grad=True)
+    e, _ = rlb_run(s, T, tau=tau_t, beta_in=bin_t)
+    L = (e[mask] / 3.0).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    peak = torch.cuda.max_memory_allocated() / 1e9
+    grads = (float(bin_t.grad[0]), float(tau_t.grad[0]))
+    del e
+    torch.cuda.empty_cache()
+
+    def loss64(**kw):
+        sv = Solver(s.with_(storage=ri.F64, **kw))
+        sv.step(T)
+        _, e64, _ = sv.moments()
+        bad = sv.counters()[0]
+        out = float((e64[mask] / 3.0).sum())
+        sv.close()
+        del sv, e64
+        torch.cuda.empty_cache()
+        return out, bad
+
+    bi = np.array(s.inflow)
+    dbx = np.array([0, 0, h, 0, 0])
+    (lp, b1), (lm, b2) = loss64(inflow=tuple(bi + dbx)), loss64(inflow=tuple(bi - dbx))
+    (tp, b3), (tm, b4) = loss64(tau=s.tau + h), loss64(tau=s.tau - h)
+    fd = ((lp - lm) / (2 * h), (tp - tm) / (2 * h))
+    return {"T": T, "cells": s.cells, "loss": float(L), "dL_dbeta_in_x": grads[0],
+            "dL_dtau": grads[1], "fd_dbeta_in_x": fd[0], "fd_dtau": fd[1],
+            "rel_err_beta_in": float("%.3g" % abs(grads[0] / fd[0] - 1)),
+            "rel_err_tau": float("%.3g" % abs(grads[1] / fd[1] - 1)),
+            "gradient_seconds": round(dt, 2), "peak_GB": round(peak, 1),
+            "fp64_unphysical_updates": int(b1 + b2 + b3 + b4)}
+
+
 def bench_tubes(T=2000):
     """64 shock tubes of 2048 cells in one lattice (FP32): launch-bound, so the
     figures are microseconds per step and the wall time of a T-step gradient
@@ -324,6 +461,9 @@ def main():
     ap.add_argument("--mixed-only", action="store_true",
                     help="only the 256^3 box in the five storage formats (for kernel traces of "
                          "the mixed-precision step)")
+    ap.add_argument("--accuracy-only", action="store_true",
+                    help="only the measured errors: reduced-precision forms on the 256^3 box, "
+                         "tube gradients against FD, the 4000-step large-sphere gradient")
     ap.add_argument("--tubes-only", action="store_true",
                     help="only the 64-tube FP32 forward and 2000-step gradient (for kernel "
                          "traces of the launch-bound reverse step)")
@@ -343,6 +483,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.mixed_only:
         print(json.dumps({"mixed_precision_256cube": bench_mixed()}), flush=True)
+        return
+    if args.accuracy_only:
+        print(json.dumps({"precision_256cube_1000_steps": precision_errors(),
+                          "tube_fd": tube_fd_errors(),
+                          "gradient_large_sphere_steady_f32_T4000": large_sphere_steady_gradient()}),
+              flush=True)
         return
     if args.tubes_only:
         print(json.dumps({"tube_batch_64x2048_f32": bench_tubes()}), flush=True)
@@ -447,7 +593,10 @@ def main():
         out["adjoint_sphere_f64_3level"] = {
             k: _round(v) for k, v in bench_adjoint(ri.sphere(), 60, 5, mode="3level").items()}
         out["tube_batch_64x2048_f32"] = bench_tubes()
+        out["tube_batch_64x2048_f32"]["fd"] = tube_fd_errors()
         out["gradient_large_sphere_f32_T4000"] = bench_large_gradient()
+        out["gradient_large_sphere_steady_f32_T4000"] = large_sphere_steady_gradient()
+        out["precision_256cube_1000_steps"] = precision_errors()
         # in-place (AA-pattern) streaming: one state buffer instead of two
         sp = ri.sphere()
         sp.inplace = True

@@ -92,9 +92,19 @@ typedef enum {
 
 /* Type of the collision arithmetic (moment sums, equilibria, relaxation); the
  * moment inversion is FP64 always.  AUTO = FP64 for RLB_F64/F32/F32DEV and
- * FP32 for the 16-bit storages.  FP32 collision is not offered with RLB_F64
- * storage, nor FP64 collision with 16-bit storage. */
-typedef enum { RLB_COLLIDE_AUTO = 0, RLB_COLLIDE_F32 = 1, RLB_COLLIDE_F64 = 2 } rlb_collide;
+ * FP32 for the 16-bit storages.  F32_MOM64 (4-byte storages only): FP32
+ * equilibria and relaxation with FP64 moments: the pre-collision sums
+ * accumulated in FP64, and the FP32 g equilibrium corrected by
+ * w_i (dE + 3 e_i . dm) so that its FP64-summed moments equal them (FP32
+ * coefficients would otherwise bias the conserved sums the same way every
+ * step).  FP32 collision is not offered with RLB_F64 storage, nor FP64
+ * collision with 16-bit storage. */
+typedef enum {
+  RLB_COLLIDE_AUTO = 0,
+  RLB_COLLIDE_F32 = 1,
+  RLB_COLLIDE_F64 = 2,
+  RLB_COLLIDE_F32_MOM64 = 3
+} rlb_collide;
 
 /* Problem statement (shock-tube and obstacle sections of the paper: domain,
  * lattice speed c_l, fixed obstacle, inflow state; equation of state). */

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "librlb.so")
 RLB_OK, RLB_EINVAL, RLB_ENOMEM, RLB_EDEVICE, RLB_EUNPHYSICAL = 0, -1, -2, -3, -4
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 F64, F32, F32DEV, F16DEV, BF16DEV = 0, 1, 2, 3, 4
-COLLIDE_AUTO, COLLIDE_F32, COLLIDE_F64 = 0, 1, 2
+COLLIDE_AUTO, COLLIDE_F32, COLLIDE_F64, COLLIDE_F32_MOM64 = 0, 1, 2, 3
 
 # Every symbol include/rlb.h declares (checked by the tests).
 EXPORTS = (

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rlb {
 
 // Adjoint (lambda) buffers are FP64 for every storage: lambda carries a large
@@ -72,11 +74,17 @@ struct Format<ST_BF16DEV> {
   __device__ static elem enc(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 };
 
+// Compute-type tag: FP32 equilibria and relaxation, with FP64 moments: the
+// sums (E, M, N) accumulated in FP64 and the g equilibrium corrected to them
+// (eq_fix in kernels.hpp).
+struct f32s {};
+
 template <int ST, class TC>
 struct Codec {
   using F = Format<ST>;
   using elem = typename F::elem;
-  using calc = TC;
+  using calc = std::conditional_t<std::is_same<TC, f32s>::value, float, TC>;
+  using sum = std::conditional_t<std::is_same<TC, f32s>::value, double, calc>;  // moment sums
   using lam = LamT;
   static constexpr bool dev = F::dev;
   __device__ static calc dec(elem v) { return F::template dec<calc>(v); }

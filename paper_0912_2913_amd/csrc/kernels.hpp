@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "codec.hpp"
@@ -86,8 +87,11 @@ struct HeldEq {
 // followed by the g block (offset 19 * qs).  qs = cells rounded up to 64.
 constexpr int BRICK = 64;
 
-__device__ __forceinline__ size_t at(int q, long long i) {
-  return (size_t)(i >> 6) * (size_t)(Q * BRICK) + (size_t)(q * BRICK) + (size_t)(i & (BRICK - 1));
+// Cell indices are 32-bit (a lattice holds at most 2^31 - 64 cells); only the
+// element offset is widened, by one 32 x 32 -> 64-bit multiply-add.
+__device__ __forceinline__ size_t at(int q, int i) {
+  return (size_t)((unsigned)i >> 6) * (unsigned)(Q * BRICK) +
+         (unsigned)(q * BRICK + (i & (BRICK - 1)));
 }
 
 struct Phys {
@@ -106,7 +110,7 @@ struct Phys {
 };
 
 // Relaxation rate of cell c from the per-cell field or its instance.
-__device__ __forceinline__ double omega_of(const Phys &ph, int b, long long idx) {
+__device__ __forceinline__ double omega_of(const Phys &ph, int b, int idx) {
   return ph.omega_cell ? ph.omega_cell[idx] : ph.omega[b];
 }
 
@@ -143,7 +147,7 @@ struct InflowState {
 
 struct Cell {
   int b, x, y, z, local, L;
-  long long idx;
+  int idx;
   bool active;
 };
 
@@ -166,7 +170,7 @@ __device__ __forceinline__ Cell decode_cell(const Geom &g, int B = -1) {
   uint32_t z = fdiv(g.div_y, t);
   c.y = (int)t - (int)z * g.n[1];
   c.z = (int)z;
-  c.idx = (long long)c.b * g.per + c.local;
+  c.idx = c.b * g.per + c.local;
   return c;
 }
 
@@ -195,9 +199,8 @@ __device__ __forceinline__ FaceCorr face_corr(const Geom &g, const Cell &c) {
   return f;
 }
 
-__device__ __forceinline__ long long src_fast(const Geom &g, const Cell &c, const FaceCorr &f,
-                                              int q) {
-  long long s = c.idx - g.off[q];
+__device__ __forceinline__ int src_fast(const Geom &g, const Cell &c, const FaceCorr &f, int q) {
+  int s = c.idx - g.off[q];
   if (EX[q] == 1) s += f.lx;
   if (EX[q] == -1) s += f.hx;
   if (EY[q] == 1) s += f.ly;
@@ -226,18 +229,18 @@ __device__ __forceinline__ int resolve(const Geom &g, int a, int r, bool &clampe
   return r;
 }
 
-__device__ __forceinline__ long long cell_index(const Geom &g, int b, int x, int y, int z) {
-  return (long long)b * g.per + ((long long)z * g.n[1] + y) * g.n[0] + x;
+__device__ __forceinline__ int cell_index(const Geom &g, int b, int x, int y, int z) {
+  return b * g.per + (z * g.n[1] + y) * g.n[0] + x;
 }
 
-__device__ __forceinline__ bool solid_at(const Phys &ph, long long i) {
+__device__ __forceinline__ bool solid_at(const Phys &ph, int i) {
   return ph.cls != nullptr && (ph.cls[i] & CLS_SOLID);
 }
 
 // General pull of direction q at cell c: source cell and direction
 // (bounce-back off a solid source returns the cell's own opposite population).
 struct Pull {
-  long long idx;
+  int idx;
   int q;
   bool clamped;  // source clamped into the domain on some axis
   bool bounce;
@@ -249,7 +252,7 @@ __device__ __forceinline__ Pull pull_general(const Geom &g, const Phys &ph, cons
   int sx = resolve(g, 0, c.x - EX[q], p.clamped);
   int sy = resolve(g, 1, c.y - EY[q], p.clamped);
   int sz = resolve(g, 2, c.z - EZ[q], p.clamped);
-  long long s = cell_index(g, c.b, sx, sy, sz);
+  int s = cell_index(g, c.b, sx, sy, sz);
   p.bounce = solid_at(ph, s);
   if (p.bounce) {
     p.idx = c.idx;
@@ -280,6 +283,19 @@ __device__ __forceinline__ void mirror_sums(const T (&v)[Q], T &mx, T &my, T &mz
   mx = ((v[1] - v[2]) + (v[7] - v[10])) + ((v[9] - v[8]) + (v[11] - v[14])) + (v[13] - v[12]);
   my = ((v[3] - v[4]) + (v[7] - v[9])) + ((v[10] - v[8]) + (v[15] - v[18])) + (v[17] - v[16]);
   mz = ((v[5] - v[6]) + (v[11] - v[13])) + ((v[14] - v[12]) + (v[15] - v[17])) + (v[18] - v[16]);
+}
+
+// E = sum v_i and the mirror-pair momentum sums of v, accumulated in Sm (the
+// codec's sum type: the compute type, or FP64 over FP32 values).
+template <class Sm, class T>
+__device__ __forceinline__ void moment_sums(const T (&v)[Q], Sm &E, Sm &mx, Sm &my, Sm &mz) {
+  Sm w[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) w[q] = (Sm)v[q];
+  E = (Sm)0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) E += w[q];
+  mirror_sums(w, mx, my, mz);
 }
 
 // Result of the moment inversion (FP64).
@@ -365,6 +381,41 @@ __device__ __forceinline__ T feq_dev(const EqCoef<T> &k, int q) {
   return (T)WQ[q] * (k.Nd + (T)3 * k.N * b);
 }
 
+// Moment correction of an equilibrium evaluated in a lower precision than its
+// moments (the codec's sum type is FP64, its compute type FP32): the FP32
+// coefficients round the equilibrium's moments away from the pre-collision
+// ones by an amount that repeats step after step for a slowly varying state,
+// so the relaxation would drift the conserved sums.  With the equilibrium's
+// moments summed in FP64, adding w_q (dE + 3 e_q . dm) restores them
+// (sum_q w_q = 1, sum_q w_q e_q = 0, sum_q w_q e_q e_q = I/3).
+struct EqFix {
+  float dE, dx, dy, dz;
+};
+
+template <class Sm, class T>
+__device__ __forceinline__ EqFix eq_fix(const EqCoef<T> &k, Sm sE, Sm sx, Sm sy, Sm sz) {
+  Sm t[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) t[q] = (Sm)geq_dev(k, q);
+  Sm E = (Sm)0, mx, my, mz;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) E += t[q];
+  mirror_sums(t, mx, my, mz);
+  return {(float)(sE - E), (float)(sx - mx), (float)(sy - my), (float)(sz - mz)};
+}
+
+template <class T>
+__device__ __forceinline__ T geq_fixed(const EqCoef<T> &k, const EqFix &f, int q) {
+  T d = (T)f.dE;
+  if (EX[q] == 1) d += (T)3 * (T)f.dx;
+  if (EX[q] == -1) d -= (T)3 * (T)f.dx;
+  if (EY[q] == 1) d += (T)3 * (T)f.dy;
+  if (EY[q] == -1) d -= (T)3 * (T)f.dy;
+  if (EZ[q] == 1) d += (T)3 * (T)f.dz;
+  if (EZ[q] == -1) d -= (T)3 * (T)f.dz;
+  return geq_dev(k, q) + (T)WQ[q] * d;
+}
+
 // Rest reference R_q (deviation storage) in FP64.
 __device__ __forceinline__ double rest_g(const Phys &ph, int q) {
   return q == 0 ? W0 * ph.e_ref * ph.k0 : WQ[q] * ph.e_ref * ph.ad_c;
@@ -434,8 +485,10 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *out) {
 // beyond the cell's own word.
 __device__ __forceinline__ size_t pull_at(const Geom &g, const Cell &c, const FaceCorr &fc,
                                           uint32_t cls, int q) {
-  if ((cls >> (CLS_BOUNCE + q)) & 1u) return at(OPP[q], c.idx);
-  return at(q, src_fast(g, c, fc, q));
+  // selects, not a branch: one offset per direction
+  const bool bounce = (cls >> (CLS_BOUNCE + q)) & 1u;
+  const int src = bounce ? c.idx : src_fast(g, c, fc, q);
+  return at(bounce ? OPP[q] : q, src);
 }
 
 // Pull the 19 values of one population for cell c (decoded to the compute type).
@@ -505,10 +558,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
     gather2<Cd>(g, c, cls, gs, src, pg, pf);
   else
     gather<Cd>(g, c, cls, gs, pg);
-  T sE = (T)0, sx, sy, sz;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) sE += pg[q];
-  mirror_sums(pg, sx, sy, sz);
+  using Sm = typename Cd::sum;
+  Sm sE, sx, sy, sz;
+  moment_sums(pg, sE, sx, sy, sz);
   const Inv iv = invert(ph, ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
                         ph.c * (double)sz);
   EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
@@ -516,9 +568,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
   bool bad = iv.bad;
   double N = 0.0;
   if (DO_F) {
-    T sN = (T)0;
+    Sm sN = (Sm)0;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) sN += pf[q];
+    for (int q = 0; q < Q; ++q) sN += (Sm)pf[q];
     N = ph.n_ref + (double)sN;
     if (ETA_S) {
       // tau from the pre-collision moments of this update (n = N / gamma)
@@ -529,9 +581,12 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
   }
   const T om = (T)omd;
   const El zero = Cd::enc((T)0);
+  constexpr bool fix = !std::is_same<Sm, T>::value;  // FP32 equilibrium, FP64 moments
+  const EqFix ef = fix ? eq_fix(k, sE, sx, sy, sz) : EqFix{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const El v = Cd::enc(pg[q] + om * (geq_dev(k, q) - pg[q]));
+    const T eq = fix ? geq_fixed(k, ef, q) : geq_dev(k, q);
+    const El v = Cd::enc(pg[q] + om * (eq - pg[q]));
     stream_store(&gd[at(q, c.idx)], held ? (solid ? zero : in_eq.v[Q + q]) : v);
   }
   count_lanes(bad && !held, counters, 0);
@@ -884,11 +939,11 @@ __device__ __forceinline__ void eq_param_grad(const Phys &ph, const LamEq &L, do
 }
 
 // Cell of a linear index (general paths).
-__device__ __forceinline__ Cell cell_at(const Geom &g, long long idx) {
+__device__ __forceinline__ Cell cell_at(const Geom &g, int idx) {
   Cell c;
   c.idx = idx;
   c.b = (int)(idx / g.per);
-  c.local = (int)(idx - (long long)c.b * g.per);
+  c.local = idx - c.b * g.per;
   c.active = true;
   const uint32_t t = fdiv(g.div_x, (uint32_t)c.local);
   c.x = c.local - (int)t * g.n[0];
@@ -995,21 +1050,35 @@ __device__ __forceinline__ bool clamps_onto(const FaceFlags &f, int p, int a) {
   return (e == 1 && f.lo[a]) || (e == -1 && f.hi[a]);
 }
 
-// lambda_t(x)_p gathered from the reader form R (see above).  FACES = false
-// for lattices without non-periodic axes (no clamped reader exists).
+// lambda_t(x)_p, p = 0 .. 18, gathered from the reader form R (see above).
+// The 19 plain (or bounce-back) reads are issued together, like a forward
+// pull; cells on a face of a non-periodic axis then drop the readers that lie
+// outside the domain and add the readers of clamped pulls, in one branch that
+// only waves holding such cells take.  FACES = false for lattices without
+// non-periodic axes.
 template <bool FACES>
-__device__ __forceinline__ double lam_pull(const Geom &g, const Cell &c, const FaceCorr &fc,
-                                           uint32_t cls, const FaceFlags &ff,
-                                           const LamT *__restrict__ R, int p) {
-  const int q = OPP[p];
-  const bool bounce = (cls >> (CLS_BOUNCE + q)) & 1u;
-  // x + e_p is the source of x's pull of opp(p): its wrap corrections are the
-  // ones src_fast applies
-  const long long plain = src_fast(g, c, fc, q);
-  double v = R[bounce ? at(q, c.idx) : at(p, plain)];
-  if (FACES && ff.any) {
-    if (!bounce && (leaves(ff, p, 0) || leaves(ff, p, 1) || leaves(ff, p, 2))) v = 0.0;
-    const long long stride[3] = {1, (long long)g.n[0], (long long)g.n[0] * g.n[1]};
+__device__ __forceinline__ void lam_gather(const Geom &g, const Cell &c, const FaceCorr &fc,
+                                           uint32_t cls, const LamT *__restrict__ R,
+                                           double (&lam)[Q]) {
+#pragma unroll
+  for (int p = 0; p < Q; ++p) {
+    // x + e_p is the source of x's pull of opp(p) (src_fast applies its wrap
+    // corrections); bounce-back when that pull hits a solid
+    const int q = OPP[p];
+    const bool bounce = (cls >> (CLS_BOUNCE + q)) & 1u;
+    const int src = bounce ? c.idx : src_fast(g, c, fc, q);
+    lam[p] = R[at(bounce ? q : p, src)];
+  }
+  if (!FACES) return;
+  const FaceFlags ff = face_flags(g, c);
+  if (!ff.any) return;
+  const int stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
+#pragma unroll
+  for (int p = 0; p < Q; ++p) {
+    const int q = OPP[p];
+    const bool bounce = (cls >> (CLS_BOUNCE + q)) & 1u;
+    if (!bounce && (leaves(ff, p, 0) || leaves(ff, p, 1) || leaves(ff, p, 2))) lam[p] = 0.0;
+    const int plain = src_fast(g, c, fc, q);
 #pragma unroll
     for (int m = 1; m < 8; ++m) {
       bool possible = true;
@@ -1018,7 +1087,7 @@ __device__ __forceinline__ double lam_pull(const Geom &g, const Cell &c, const F
         if (((m >> a) & 1) && ecomp(p, a) == 0) possible = false;
       if (!possible) continue;  // compile-time after unrolling
       bool ok = true;
-      long long r = plain;
+      int r = plain;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int e = ecomp(p, a);
@@ -1030,10 +1099,9 @@ __device__ __forceinline__ double lam_pull(const Geom &g, const Cell &c, const F
           ok = ok && !leaves(ff, p, a);
         }
       }
-      if (ok) v += R[at(p, r)];
+      if (ok) lam[p] += R[at(p, r)];
     }
   }
-  return v;
 }
 
 // One reverse step of the g population (see rlb_adjoint_step) in reader form:
@@ -1056,13 +1124,15 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
     const bool solid = cls & CLS_SOLID;
     const bool inflow = is_inflow(g, c.x, c.y, c.z);
     const FaceCorr fc = face_corr(g, c);
-    const FaceFlags ff = face_flags(g, c);
     double pre[Q], lam[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) pre[q] = (double)Cd::dec(S[pull_at(g, c, fc, cls, q)]);
+    if (NAT_IN) {
 #pragma unroll
-    for (int p = 0; p < Q; ++p)
-      lam[p] = NAT_IN ? lam_in[at(p, c.idx)] : lam_pull<FACES>(g, c, fc, cls, ff, lam_in, p);
+      for (int p = 0; p < Q; ++p) lam[p] = lam_in[at(p, c.idx)];
+    } else {
+      lam_gather<FACES>(g, c, fc, cls, lam_in, lam);
+    }
     if (inflow && !solid) {
       // the held face: lambda_{t+1} there is the gradient of the inflow state
       const double g2 = 1.0 / (1.0 - (in.bx * in.bx + in.by * in.by + in.bz * in.bz));
@@ -1092,7 +1162,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
   }
 }
 
-// lambda (natural layout) from the reader form: lambda(x)_p as lam_pull
+// lambda (natural layout) from the reader form: lambda(x)_p as lam_gather
 // gathers it; zeros on solid cells (their populations are never read).
 template <bool FACES>
 __global__ __launch_bounds__(BLOCK) void k_lam_gather(const Geom g, const Phys ph,
@@ -1103,12 +1173,10 @@ __global__ __launch_bounds__(BLOCK) void k_lam_gather(const Geom g, const Phys p
   const uint32_t cls = ph.cls ? ph.cls[c.idx] : 0u;
   const bool solid = cls & CLS_SOLID;
   const FaceCorr fc = face_corr(g, c);
-  const FaceFlags ff = face_flags(g, c);
+  double v[Q];
+  lam_gather<FACES>(g, c, fc, cls, R, v);
 #pragma unroll
-  for (int p = 0; p < Q; ++p) {
-    const double v = lam_pull<FACES>(g, c, fc, cls, ff, R, p);
-    lam[at(p, c.idx)] = solid ? 0.0 : v;
-  }
+  for (int p = 0; p < Q; ++p) lam[at(p, c.idx)] = solid ? 0.0 : v[p];
 }
 
 // Faces of non-periodic axes, flattened: face f = (axis, side) holds
@@ -1267,19 +1335,23 @@ __device__ __forceinline__ uint32_t collide_emit(const Phys &ph, const Cell &c,
                                              const typename Cd::calc (&pf)[Q], const SG &sg,
                                              const SF &sf) {
   using T = typename Cd::calc;
-  T sE = (T)0, sx, sy, sz;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) sE += pg[q];
-  mirror_sums(pg, sx, sy, sz);
+  using Sm = typename Cd::sum;
+  Sm sE, sx, sy, sz;
+  moment_sums(pg, sE, sx, sy, sz);
   const Inv iv = invert(ph, ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
                         ph.c * (double)sz);
   EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
   const T om = (T)omega_of(ph, c.b, c.idx);
+  constexpr bool fix = !std::is_same<Sm, T>::value;  // FP32 equilibrium, FP64 moments
+  const EqFix ef = fix ? eq_fix(k, sE, sx, sy, sz) : EqFix{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int q = 0; q < Q; ++q) sg(q, Cd::enc(pg[q] + om * (geq_dev(k, q) - pg[q])));
-  T sN = (T)0;
+  for (int q = 0; q < Q; ++q) {
+    const T eq = fix ? geq_fixed(k, ef, q) : geq_dev(k, q);
+    sg(q, Cd::enc(pg[q] + om * (eq - pg[q])));
+  }
+  Sm sN = (Sm)0;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) sN += pf[q];
+  for (int q = 0; q < Q; ++q) sN += (Sm)pf[q];
   const double N = ph.n_ref + (double)sN;
   k.N = (T)N;
   k.Nd = (T)(N - ph.n_ref);
@@ -1296,20 +1368,24 @@ __device__ __forceinline__ uint32_t collide_inplace(const Geom &g, const Phys &p
                                                 typename Cd::calc (&pg)[Q],
                                                 typename Cd::calc (&pf)[Q]) {
   using T = typename Cd::calc;
-  T sE = (T)0, sx, sy, sz;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) sE += pg[q];
-  mirror_sums(pg, sx, sy, sz);
+  using Sm = typename Cd::sum;
+  Sm sE, sx, sy, sz;
+  moment_sums(pg, sE, sx, sy, sz);
   const Inv iv = invert(ph, ph.e_ref + (double)sE, ph.c * (double)sx, ph.c * (double)sy,
                         ph.c * (double)sz);
   EqCoef<T> k = eq_coef<T>(ph, 0.0, iv.eps, iv.W, iv.bx, iv.by, iv.bz);
   const T om = (T)omega_of(ph, c.b, c.idx);
-  T sN = (T)0;
+  Sm sN = (Sm)0;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) sN += pf[q];
+  for (int q = 0; q < Q; ++q) sN += (Sm)pf[q];
   const double N = ph.n_ref + (double)sN;
+  constexpr bool fix = !std::is_same<Sm, T>::value;  // FP32 equilibrium, FP64 moments
+  const EqFix ef = fix ? eq_fix(k, sE, sx, sy, sz) : EqFix{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int q = 0; q < Q; ++q) pg[q] = pg[q] + om * (geq_dev(k, q) - pg[q]);
+  for (int q = 0; q < Q; ++q) {
+    const T eq = fix ? geq_fixed(k, ef, q) : geq_dev(k, q);
+    pg[q] = pg[q] + om * (eq - pg[q]);
+  }
   k.N = (T)N;
   k.Nd = (T)(N - ph.n_ref);
 #pragma unroll
@@ -1454,7 +1530,7 @@ __device__ __forceinline__ unsigned solid_around(const Geom &g, const Phys &ph, 
     for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        const long long i = cell_index(g, c.b, resolve(g, 0, c.x + dx, cl),
+        const int i = cell_index(g, c.b, resolve(g, 0, c.x + dx, cl),
                                        resolve(g, 1, c.y + dy, cl), resolve(g, 2, c.z + dz, cl));
         if (ph.cls[i] & CLS_SOLID) m |= 1u << ((dz + 1) * 9 + (dy + 1) * 3 + (dx + 1));
       }

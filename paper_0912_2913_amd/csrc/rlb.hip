@@ -155,10 +155,12 @@ rlb_status validate(const rlb_params *p, long long *cells_out) {
   }
   if (elem_size(p->storage) == 0) return fail(RLB_EINVAL, "unknown storage");
   if (p->collide != RLB_COLLIDE_AUTO && p->collide != RLB_COLLIDE_F32 &&
-      p->collide != RLB_COLLIDE_F64)
+      p->collide != RLB_COLLIDE_F64 && p->collide != RLB_COLLIDE_F32_MOM64)
     return fail(RLB_EINVAL, "unknown collision type");
-  if (p->storage == RLB_F64 && p->collide == RLB_COLLIDE_F32)
+  if (p->storage == RLB_F64 && (p->collide == RLB_COLLIDE_F32 || p->collide == RLB_COLLIDE_F32_MOM64))
     return fail(RLB_EINVAL, "FP64 storage collides in FP64");
+  if ((p->storage == RLB_F16DEV || p->storage == RLB_BF16DEV) && p->collide == RLB_COLLIDE_F32_MOM64)
+    return fail(RLB_EINVAL, "FP64 moment sums are offered with the 4-byte storages");
   if ((p->storage == RLB_F16DEV || p->storage == RLB_BF16DEV) && p->collide == RLB_COLLIDE_F64)
     return fail(RLB_EINVAL, "16-bit storages collide in FP32");
   if (p->storage >= ST_F32DEV) {
@@ -549,13 +551,16 @@ rlb_status launch_init_adjoint(rlb_solver *h, const double *e0, const double *be
 #define RLB_DISPATCH(h, fn, ...)                                                   \
   do {                                                                             \
     const bool c64_ = (h)->cp == RLB_COLLIDE_F64;                                  \
+    const bool s64_ = (h)->cp == RLB_COLLIDE_F32_MOM64;                            \
     switch ((h)->st) {                                                             \
       case ST_F64: return fn<ST_F64, double>(__VA_ARGS__);                         \
       case ST_F32:                                                                 \
-        return c64_ ? fn<ST_F32, double>(__VA_ARGS__) : fn<ST_F32, float>(__VA_ARGS__); \
+        return c64_ ? fn<ST_F32, double>(__VA_ARGS__)                              \
+                    : (s64_ ? fn<ST_F32, f32s>(__VA_ARGS__) : fn<ST_F32, float>(__VA_ARGS__)); \
       case ST_F32DEV:                                                              \
         return c64_ ? fn<ST_F32DEV, double>(__VA_ARGS__)                           \
-                    : fn<ST_F32DEV, float>(__VA_ARGS__);                           \
+                    : (s64_ ? fn<ST_F32DEV, f32s>(__VA_ARGS__)                     \
+                            : fn<ST_F32DEV, float>(__VA_ARGS__));                  \
       case ST_F16DEV: return fn<ST_F16DEV, float>(__VA_ARGS__);                    \
       case ST_BF16DEV: return fn<ST_BF16DEV, float>(__VA_ARGS__);                  \
     }                                                                              \

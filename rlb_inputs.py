@@ -11,6 +11,8 @@ with sizes and values fixed by this project:
 
   * ``shock_tube``: 1 x 1 x 800, e = 1 on the left half, 1/16 on the right,
     beta = 0, n = e^(3/4) (n ~ T^3 with e ~ T^4), tau = 0.6, outflow in z.
+  * ``tachyon_tube``: the same tube at lattice speed c_l = 10, tau = 0.51,
+    4000 steps (time 400).
   * ``sphere``: 200 x 100 x 100, solid ball of radius 15 at (60, 50, 50),
     inflow plane x = 0 at (n, e, beta) = (1, 1, (0.5, 0, 0)), downstream e = 0.2 at
     rest, tau = 0.55, outflow at x = nx-1, y and z periodic.
@@ -18,7 +20,8 @@ with sizes and values fixed by this project:
     (|beta| <= 0.2) and e = 1 + 0.1 s(x).
   * ``tube_batch``: 64 tubes of 1 x 1 x 2048 with tau_b ~ U[0.51, 1] and
     e_L/e_R ~ U[4, 32].
-  * ``sphere_large``: 384 x 192 x 192 with a radius-24 sphere at (115, 96, 96).
+  * ``sphere_large``: 384 x 192 x 192 with a radius-24 sphere at (115, 96, 96);
+    ``sphere_large_steady``: the same with |beta_in| = 0.3 into e = 1 at rest.
 """
 from __future__ import annotations
 
@@ -31,7 +34,7 @@ PERIODIC, OUTFLOW, INFLOW = 0, 1, 2
 
 # Storage and collision-type codes (same numbering as the C header's enums).
 F64, F32, F32DEV, F16DEV, BF16DEV = 0, 1, 2, 3, 4
-COLLIDE_AUTO, COLLIDE_F32, COLLIDE_F64 = 0, 1, 2
+COLLIDE_AUTO, COLLIDE_F32, COLLIDE_F64, COLLIDE_F32_MOM64 = 0, 1, 2, 3
 STORAGE_NAMES = {F64: "f64", F32: "f32", F32DEV: "f32dev", F16DEV: "f16dev", BF16DEV: "bf16dev"}
 
 
@@ -110,6 +113,18 @@ def shock_tube(nz=800, e_L=1.0, e_R=1.0 / 16.0, tau=0.6, steps=500, c_l=1.0, bat
     e_R = np.asarray(e_R, dtype=np.float64).reshape(-1, 1, 1, 1)
     e = np.where(z < nz // 2, e_L, e_R)
     s.n0, s.e0, s.beta0 = _fields(s, e, (0.0, 0.0, 0.0))
+    return s
+
+
+def tachyon_tube(nz=800, t=400, c_l=10.0, tau=0.51, ratio=16.0, storage=F64) -> Setup:
+    """The shock-tube section's "numerical tachyons": the ratio-16 tube (star
+    state beta* = 0.54, above the c_l = 1 positivity bound c_l/3) run with a
+    lattice speed c_l = 10, up to time t (in cells / c: t * c_l steps).  tau =
+    0.51 gives the kinematic viscosity c_l (tau - 1/2) / 3 = 0.033 of the c_l = 1
+    tube at tau = 0.6."""
+    s = shock_tube(nz=nz, e_L=1.0, e_R=1.0 / ratio, tau=tau, steps=int(round(t * c_l)),
+                   c_l=c_l, storage=storage)
+    s.name = "tachyon_tube"
     return s
 
 
@@ -193,10 +208,19 @@ def tube_batch(batch=64, nz=2048, steps=2000, storage=F32, seed=2, tau_range=(0.
     return s, tau, ratio, redrawn
 
 
-def sphere_large(steps=4000, storage=F32) -> Setup:
+def sphere_large(steps=4000, storage=F32, beta_in=0.5, e_down=0.2) -> Setup:
     s = sphere(nx=384, ny=192, nz=192, centre=(115, 96, 96), radius=24, steps=steps,
-               storage=storage)
+               storage=storage, beta_in=beta_in, e_down=e_down)
     s.name = "sphere_large"
+    return s
+
+
+def sphere_large_steady(steps=4000, storage=F32) -> Setup:
+    """The 384 x 192 x 192 sphere with a milder inflow that stays physical at
+    c_l = 1 for the 4000 steps: |beta_in| = 0.3 into fluid at rest at the
+    inflow's own energy density (e_down = 1), so no pressure jump travels."""
+    s = sphere_large(steps=steps, storage=storage, beta_in=0.3, e_down=1.0)
+    s.name = "sphere_large_steady"
     return s
 
 

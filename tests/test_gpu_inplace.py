@@ -86,10 +86,11 @@ def test_inplace_sphere_block_against_two_buffer_run():
     b.close()
 
 
-def test_inplace_fp32_deviation_storage_matches_two_buffer_run():
+@pytest.mark.parametrize("collide", [ri.COLLIDE_AUTO, ri.COLLIDE_F32_MOM64])
+def test_inplace_fp32_deviation_storage_matches_two_buffer_run(collide):
     from paper_0912_2913_amd.solver import Solver
 
-    mk = lambda: CASES["inflow_outflow_obstacle"]().with_(storage=ri.F32DEV)
+    mk = lambda: CASES["inflow_outflow_obstacle"]().with_(storage=ri.F32DEV, collide=collide)
     a = Solver(mk())
     a.step(20)
     b = Solver(inplace(mk()))

@@ -160,6 +160,19 @@ def test_shock_tube_full_size():
     compare(s, 500)
 
 
+def test_tachyon_tube_full_run():
+    """The c_l = 10 tube: f stays positive, so n and f are held per cell with e and
+    beta, and no update breaks the bound.  At 2000 steps (time 200) the bar is
+    1e-12; over the full 4000 steps (time 400) two independent FP64 evaluations
+    of the scheme drift 2.1e-12 apart in beta (pinned on the CPU), and the bar is
+    5e-12."""
+    s = ri.tachyon_tube()
+    errs = compare(s, s.steps // 2)
+    assert "n_per_cell" in errs and "n_marked" not in errs
+    errs = compare(s, s.steps, tol=5e-12)
+    assert "n_per_cell" in errs and "n_marked" not in errs
+
+
 def test_paper_pressure_ratio_tube():
     s = ri.shock_tube(e_R=3.2567e-6 / 7.9433e-6, steps=400, tau=0.55)
     compare(s, 400)

@@ -50,6 +50,7 @@ def test_mixed_precision_box_256_1000_steps():
     errs = {}
     for st, collide in [(ri.F32, ri.COLLIDE_AUTO), (ri.F32DEV, ri.COLLIDE_AUTO),
                         (ri.F32, ri.COLLIDE_F32), (ri.F32DEV, ri.COLLIDE_F32),
+                        (ri.F32DEV, ri.COLLIDE_F32_MOM64),
                         (ri.F16DEV, ri.COLLIDE_AUTO), (ri.BF16DEV, ri.COLLIDE_AUTO)]:
         s = ri.periodic_box(storage=st)
         s.collide = collide
@@ -66,15 +67,24 @@ def test_mixed_precision_box_256_1000_steps():
     for name in ("f32", "f32dev"):
         ee, eb = errs[(name, ri.COLLIDE_F32)]
         assert ee <= 1e-4 and eb <= 1e-4, (name, ee, eb)
+    # FP32 deviations with FP32 equilibria and relaxation whose moments are
+    # summed and corrected in FP64: the 1e-5 target in that form (measured
+    # 1.1e-6 in e, 2.4e-6 in beta)
+    ee, eb = errs[("f32dev", ri.COLLIDE_F32_MOM64)]
+    assert ee <= 1e-5 and eb <= 1e-5, (ee, eb)
     for st in (ri.F16DEV, ri.BF16DEV):
         ee, eb = errs[(ri.STORAGE_NAMES[st], ri.COLLIDE_AUTO)]
         assert ee <= TOL_16[st] and eb <= TOL_16[st], (st, ee, eb)
 
 
-@pytest.mark.parametrize("st", [ri.F32, ri.F32DEV, ri.F16DEV, ri.BF16DEV])
-def test_mixed_precision_small_box_against_oracle(st):
+@pytest.mark.parametrize("st,collide", [(ri.F32, ri.COLLIDE_AUTO), (ri.F32DEV, ri.COLLIDE_AUTO),
+                                        (ri.F32DEV, ri.COLLIDE_F32_MOM64),
+                                        (ri.F16DEV, ri.COLLIDE_AUTO),
+                                        (ri.BF16DEV, ri.COLLIDE_AUTO)])
+def test_mixed_precision_small_box_against_oracle(st, collide):
     """32^3 periodic box, 200 steps, each storage against the FP64 oracle."""
     s = ri.periodic_box(n=32, storage=st, beta_max=0.2)
+    s.collide = collide
     p = problem(s)
     S = oracle.init(p, s.n0, s.e0, s.beta0)
     oracle.run(p, S, 200)
@@ -238,3 +248,55 @@ def test_large_sphere_adjoint_surface_pressure(storage, tol):
     print("large sphere", ri.STORAGE_NAMES[storage], got, (fd_b, fd_t, fd_v))
     for g_, f_ in zip(got, (fd_b, fd_t, fd_v)):
         assert g_ == pytest.approx(f_, rel=tol)
+
+
+@pytest.mark.timeout(900)
+def test_large_sphere_steady_inflow_gradient_T4000(capsys):
+    """The 384 x 192 x 192 sphere with |beta_in| = 0.3 into fluid at the inflow's
+    energy density stays physical over 4000 steps at c_l = 1: the sqrt(T)
+    gradient of the surface pressure (FP32 storage) with respect to the inflow
+    velocity and tau is a physical value, checked against central FD of FP64 GPU
+    runs at the bound of FP32 storage (the tube workload's conditioning
+    argument)."""
+    from paper_0912_2913_amd.autograd import rlb_run, surface_mask
+
+    T = 4000
+    dev = "cuda:0"
+    s = ri.sphere_large_steady(steps=T, storage=ri.F32)
+    mask = torch.as_tensor(surface_mask(s), device=dev)
+    bin_t = torch.tensor(s.inflow[2:5], dtype=torch.float64, device=dev, requires_grad=True)
+    tau_t = torch.tensor(s.tau, device=dev, requires_grad=True)
+    with capsys.disabled():
+        print("\n[large sphere T=4000] FP32 gradient", flush=True)
+    e, _ = rlb_run(s, T, tau=tau_t, beta_in=bin_t)
+    L = (e[mask] / 3.0).sum()
+    L.backward()
+    assert torch.isfinite(L) and torch.isfinite(e).all()
+    del e
+    torch.cuda.empty_cache()
+
+    def loss64(**kw):
+        from paper_0912_2913_amd.solver import Solver
+
+        sv = Solver(s.with_(storage=ri.F64, **kw))
+        sv.step(T)
+        _, e64, _ = sv.moments()
+        assert sv.counters()[0] == 0
+        out = float((e64[mask] / 3.0).sum())
+        sv.close()
+        del sv, e64
+        torch.cuda.empty_cache()
+        with capsys.disabled():
+            print("[large sphere T=4000] FP64 run done", flush=True)
+        return out
+
+    h = 1e-6
+    bi = np.array(s.inflow)
+    dbx = np.array([0, 0, h, 0, 0])
+    fd_b = (loss64(inflow=tuple(bi + dbx)) - loss64(inflow=tuple(bi - dbx))) / (2 * h)
+    fd_t = (loss64(tau=s.tau + h) - loss64(tau=s.tau - h)) / (2 * h)
+    got = (float(bin_t.grad[0]), float(tau_t.grad[0]))
+    with capsys.disabled():
+        print("[large sphere T=4000] gradient", got, "FD", (fd_b, fd_t), flush=True)
+    for g_, f_ in zip(got, (fd_b, fd_t)):
+        assert g_ == pytest.approx(f_, rel=TUBE_FP32_TOL)
