@@ -1050,13 +1050,24 @@ __device__ __forceinline__ bool clamps_onto(const FaceFlags &f, int p, int a) {
   return (e == 1 && f.lo[a]) || (e == -1 && f.hi[a]);
 }
 
+// Which face corrections a lattice needs in the reverse gather: none (every
+// axis periodic), one non-periodic axis of extent > 1 (the axis is part of
+// the kernel), or the general case.
+enum : int { FACES_NONE = 0, FACES_X = 1, FACES_Y = 2, FACES_Z = 3, FACES_ANY = 4 };
+
 // lambda_t(x)_p, p = 0 .. 18, gathered from the reader form R (see above).
 // The 19 plain (or bounce-back) reads are issued together, like a forward
 // pull; cells on a face of a non-periodic axis then drop the readers that lie
 // outside the domain and add the readers of clamped pulls, in one branch that
-// only waves holding such cells take.  FACES = false for lattices without
-// non-periodic axes.
-template <bool FACES>
+// only waves holding such cells take.
+//
+// With one non-periodic axis A, a cell on its low face has a clamped reader
+// for each of the five directions p with e_pA = +1 (and loses its reader for
+// opp(p)), a cell on its high face for each opp(p) (and loses p); the reader
+// is the plain one moved back onto the face along A.  One select-addressed
+// load per pair serves both faces, all five issued together.  Several
+// non-periodic axes take the general loop over clamp patterns.
+template <int FACES>
 __device__ __forceinline__ void lam_gather(const Geom &g, const Cell &c, const FaceCorr &fc,
                                            uint32_t cls, const LamT *__restrict__ R,
                                            double (&lam)[Q]) {
@@ -1069,7 +1080,34 @@ __device__ __forceinline__ void lam_gather(const Geom &g, const Cell &c, const F
     const int src = bounce ? c.idx : src_fast(g, c, fc, q);
     lam[p] = R[at(bounce ? q : p, src)];
   }
-  if (!FACES) return;
+  if (FACES == FACES_NONE) return;
+  if (FACES != FACES_ANY) {
+    constexpr int A = FACES - 1;
+    const int co = A == 0 ? c.x : (A == 1 ? c.y : c.z);
+    const bool lo = co == 0, hi = co == g.n[A] - 1;
+    if (!(lo || hi)) return;
+    const int sA = A == 0 ? 1 : (A == 1 ? g.n[0] : g.n[0] * g.n[1]);
+    double v[Q];
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+      if (ecomp(p, A) != 1) continue;  // compile-time after unrolling
+      const int m = OPP[p];
+      // low face: the reader of p, x + e_p moved back onto the face along A;
+      // high face: the reader of m, x + e_m moved forward onto it
+      const int r = lo ? src_fast(g, c, fc, m) - sA : src_fast(g, c, fc, p) + sA;
+      v[p] = R[at(lo ? p : m, r)];
+    }
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+      if (ecomp(p, A) != 1) continue;
+      const int m = OPP[p];
+      const bool bp = (cls >> (CLS_BOUNCE + m)) & 1u;  // x's pull of opp(p) bounces
+      const bool bm = (cls >> (CLS_BOUNCE + p)) & 1u;  // x's pull of opp(m) bounces
+      lam[p] = lo ? lam[p] + v[p] : (bp ? lam[p] : 0.0);
+      lam[m] = hi ? lam[m] + v[p] : (bm ? lam[m] : 0.0);
+    }
+    return;
+  }
   const FaceFlags ff = face_flags(g, c);
   if (!ff.any) return;
   const int stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
@@ -1111,7 +1149,7 @@ __device__ __forceinline__ void lam_gather(const Geom &g, const Cell &c, const F
 // per workgroup in step order, then reduces once): part[L][5] = (dL/dtau,
 // dL/de_in, dL/dbeta_in[3]).  Held cells (solid, inflow) run the common path
 // and store zeros, so that every lane joins the same full-wavefront stores.
-template <int ST, class TC, bool NAT_IN, bool FACES>
+template <int ST, class TC, bool NAT_IN, int FACES>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(
     const Geom g, const Phys ph, const typename Codec<ST, TC>::elem *__restrict__ S,
     const LamT *__restrict__ lam_in, LamT *__restrict__ R_out, double *__restrict__ part,
@@ -1164,7 +1202,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
 
 // lambda (natural layout) from the reader form: lambda(x)_p as lam_gather
 // gathers it; zeros on solid cells (their populations are never read).
-template <bool FACES>
+template <int FACES>
 __global__ __launch_bounds__(BLOCK) void k_lam_gather(const Geom g, const Phys ph,
                                                       const LamT *__restrict__ R,
                                                       LamT *__restrict__ lam) {

@@ -42,6 +42,7 @@ struct rlb_solver {
   Phys ph;
   InflowState in;
   Faces faces;
+  int face_mode;  // FACES_* of the reverse gather
   int st, cp;
   size_t elem, lam_elem;
   void *pop[2];
@@ -230,6 +231,16 @@ void setup_geometry(rlb_solver *h) {
     }
   }
   F.start[F.count] = acc;
+  // one non-periodic axis of extent > 1: the reverse gather specialised to it
+  int np_axes = 0, np_axis = -1;
+  for (int a = 0; a < 3; ++a)
+    if (!g.periodic[a]) {
+      ++np_axes;
+      np_axis = a;
+    }
+  h->face_mode = np_axes == 0 ? FACES_NONE
+                 : (np_axes == 1 && g.n[np_axis] > 1) ? FACES_X + np_axis
+                                                      : FACES_ANY;
 }
 
 unsigned grid_blocks(const rlb_solver *h) { return (unsigned)h->g.nblk; }
@@ -458,23 +469,25 @@ rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_in, bool
                           void *R_out) {
   using El = typename Codec<ST, TC>::elem;
   const int accum = h->rev_pending ? 1 : 0;
-  const bool faces = h->faces.count > 0;
   const dim3 grid(grid_blocks(h)), block(BLOCK);
   const El *s = (const El *)S;
   const LamT *li = (const LamT *)lam_in;
   LamT *ro = (LamT *)R_out;
-  if (nat_in && faces)
-    hipLaunchKernelGGL((k_adjoint<ST, TC, true, true>), grid, block, 0, h->stream, h->g, h->ph, s,
-                       li, ro, h->d_part_rev, h->in, accum);
-  else if (nat_in)
-    hipLaunchKernelGGL((k_adjoint<ST, TC, true, false>), grid, block, 0, h->stream, h->g, h->ph, s,
-                       li, ro, h->d_part_rev, h->in, accum);
-  else if (faces)
-    hipLaunchKernelGGL((k_adjoint<ST, TC, false, true>), grid, block, 0, h->stream, h->g, h->ph, s,
-                       li, ro, h->d_part_rev, h->in, accum);
-  else
-    hipLaunchKernelGGL((k_adjoint<ST, TC, false, false>), grid, block, 0, h->stream, h->g, h->ph,
-                       s, li, ro, h->d_part_rev, h->in, accum);
+#define RLB_ADJ(NAT, FM)                                                                       \
+  hipLaunchKernelGGL((k_adjoint<ST, TC, NAT, FM>), grid, block, 0, h->stream, h->g, h->ph, s, li, \
+                     ro, h->d_part_rev, h->in, accum)
+  if (nat_in) {
+    RLB_ADJ(true, FACES_NONE);  // a natural input reads no neighbours
+  } else {
+    switch (h->face_mode) {
+      case FACES_NONE: RLB_ADJ(false, FACES_NONE); break;
+      case FACES_X: RLB_ADJ(false, FACES_X); break;
+      case FACES_Y: RLB_ADJ(false, FACES_Y); break;
+      case FACES_Z: RLB_ADJ(false, FACES_Z); break;
+      default: RLB_ADJ(false, FACES_ANY); break;
+    }
+  }
+#undef RLB_ADJ
   h->rev_pending = true;
   RLB_HIP(hipGetLastError());
   return RLB_OK;
@@ -482,12 +495,26 @@ rlb_status launch_adjoint(rlb_solver *h, const void *S, const void *lam_in, bool
 
 // Natural lambda from its reader form.
 rlb_status launch_lam_gather(rlb_solver *h, const void *R, void *lam) {
-  if (h->faces.count > 0)
-    hipLaunchKernelGGL(k_lam_gather<true>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
-                       h->ph, (const LamT *)R, (LamT *)lam);
-  else
-    hipLaunchKernelGGL(k_lam_gather<false>, dim3(grid_blocks(h)), dim3(BLOCK), 0, h->stream, h->g,
-                       h->ph, (const LamT *)R, (LamT *)lam);
+  const dim3 grid(grid_blocks(h)), block(BLOCK);
+  const LamT *r = (const LamT *)R;
+  LamT *l = (LamT *)lam;
+  switch (h->face_mode) {
+    case FACES_NONE:
+      hipLaunchKernelGGL(k_lam_gather<FACES_NONE>, grid, block, 0, h->stream, h->g, h->ph, r, l);
+      break;
+    case FACES_X:
+      hipLaunchKernelGGL(k_lam_gather<FACES_X>, grid, block, 0, h->stream, h->g, h->ph, r, l);
+      break;
+    case FACES_Y:
+      hipLaunchKernelGGL(k_lam_gather<FACES_Y>, grid, block, 0, h->stream, h->g, h->ph, r, l);
+      break;
+    case FACES_Z:
+      hipLaunchKernelGGL(k_lam_gather<FACES_Z>, grid, block, 0, h->stream, h->g, h->ph, r, l);
+      break;
+    default:
+      hipLaunchKernelGGL(k_lam_gather<FACES_ANY>, grid, block, 0, h->stream, h->g, h->ph, r, l);
+      break;
+  }
   RLB_HIP(hipGetLastError());
   return RLB_OK;
 }

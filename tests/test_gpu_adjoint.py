@@ -30,6 +30,10 @@ def setups():
             8, 9, 7, seed=204, tau=[0.75],
             bc=((ri.OUTFLOW, ri.INFLOW), (ri.OUTFLOW, ri.OUTFLOW), (ri.PERIODIC, ri.PERIODIC)),
             inflow=(1.0, 0.95, -0.1, 0.05, 0.0), solid_centre=(0, 4, 3), solid_radius=2.0),
+        "inflow_x_solid_on_outflow_face": ri.random_state_setup(
+            11, 6, 7, batch=2, seed=206, tau=[0.7, 0.95],
+            bc=((ri.INFLOW, ri.OUTFLOW), (ri.PERIODIC, ri.PERIODIC), (ri.PERIODIC, ri.PERIODIC)),
+            inflow=(1.0, 1.02, 0.12, 0.02, -0.03), solid_centre=(10, 3, 3), solid_radius=1.8),
         "tube_batch": ri.shock_tube(nz=67, e_L=1.0, e_R=0.3, tau=0.7, batch=3),
         "tachyon": ri.random_state_setup(6, 7, 5, seed=205, tau=[0.9], c_l=2.0,
                                          bc=((ri.PERIODIC, ri.PERIODIC), (ri.OUTFLOW, ri.OUTFLOW),
@@ -308,7 +312,8 @@ def test_adjoint_sweep_equals_pending_adjoint_steps(name):
     sv.close()
 
 
-@pytest.mark.parametrize("name", ["inflow_outflow_obstacle", "outflow_corners", "tube_batch"])
+@pytest.mark.parametrize("name", ["inflow_outflow_obstacle", "outflow_corners",
+                                  "inflow_x_solid_on_outflow_face", "tube_batch"])
 def test_reader_form_segments_equal_step_by_step(name):
     """Segments chained in reader form (a checkpoint read in place plus its
     successors per call, one gather at the end) give the lambda and the
@@ -481,7 +486,8 @@ STORAGES = [ri.F32, ri.F32DEV, ri.F16DEV, ri.BF16DEV]
 
 
 @pytest.mark.parametrize("storage", STORAGES, ids=[ri.STORAGE_NAMES[v] for v in STORAGES])
-@pytest.mark.parametrize("name", ["inflow_outflow_obstacle", "outflow_corners", "tachyon"])
+@pytest.mark.parametrize("name", ["inflow_outflow_obstacle", "outflow_corners",
+                                  "inflow_x_solid_on_outflow_face", "tachyon"])
 def test_reverse_entry_points_every_storage_match_oracle(name, storage):
     """The reverse arithmetic is FP64 for every storage: on the GPU's own state
     (a few forward steps in the storage format), decoded to FP64, the adjoint
