@@ -491,28 +491,55 @@ __device__ __forceinline__ size_t pull_at(const Geom &g, const Cell &c, const Fa
   return at(bounce ? OPP[q] : q, src);
 }
 
-// Pull the 19 values of one population for cell c (decoded to the compute type).
-template <class Cd>
+// A wave holds a cell with a solid pull source (the cell word's near bit).
+// Such waves are few (the cells next to an obstacle).  For 4- and 8-byte
+// populations the pulls below are issued with the plain offsets before the
+// cell word has arrived, and only these waves pull again with the bounce-back
+// offsets, so that no wave waits for its cell words before its population
+// loads.  The 16-bit forms are issue-bound: there the second pull's code costs
+// more than the wait, and the offsets are selected from the cell word.
+__device__ __forceinline__ bool wave_near_solid(uint32_t cls) {
+  return __builtin_amdgcn_ballot_w64((cls & CLS_NEAR) != 0u) != 0u;
+}
+
+// Pull the 19 values of one population for cell c (decoded to the compute
+// type).  HELD = false: no cell word (lattice without solid cells).
+template <class Cd, bool HELD>
 __device__ __forceinline__ void gather(const Geom &g, const Cell &c, uint32_t cls,
                                        const typename Cd::elem *__restrict__ P,
                                        typename Cd::calc (&v)[Q]) {
+  constexpr bool early = sizeof(typename Cd::elem) >= 4;
   const FaceCorr fc = face_corr(g, c);
 #pragma unroll
-  for (int q = 0; q < Q; ++q) v[q] = Cd::dec(P[pull_at(g, c, fc, cls, q)]);
+  for (int q = 0; q < Q; ++q)
+    v[q] = Cd::dec(P[early ? at(q, src_fast(g, c, fc, q)) : pull_at(g, c, fc, cls, q)]);
+  if (early && HELD && wave_near_solid(cls)) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = Cd::dec(P[pull_at(g, c, fc, cls, q)]);
+  }
 }
 
 // Both populations of cell c, pulled in one pass (same sources for f and g).
-template <class Cd>
+template <class Cd, bool HELD>
 __device__ __forceinline__ void gather2(const Geom &g, const Cell &c, uint32_t cls,
                                         const typename Cd::elem *__restrict__ G,
                                         const typename Cd::elem *__restrict__ F,
                                         typename Cd::calc (&vg)[Q], typename Cd::calc (&vf)[Q]) {
+  constexpr bool early = sizeof(typename Cd::elem) >= 4;
   const FaceCorr fc = face_corr(g, c);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const size_t o = pull_at(g, c, fc, cls, q);
+    const size_t o = early ? at(q, src_fast(g, c, fc, q)) : pull_at(g, c, fc, cls, q);
     vg[q] = Cd::dec(G[o]);
     vf[q] = Cd::dec(F[o]);
+  }
+  if (early && HELD && wave_near_solid(cls)) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const size_t o = pull_at(g, c, fc, cls, q);
+      vg[q] = Cd::dec(G[o]);
+      vf[q] = Cd::dec(F[o]);
+    }
   }
 }
 
@@ -555,9 +582,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
   // flight per wave); g then f are relaxed and streamed out.
   T pg[Q], pf[Q];
   if (DO_F)
-    gather2<Cd>(g, c, cls, gs, src, pg, pf);
+    gather2<Cd, HELD>(g, c, cls, gs, src, pg, pf);
   else
-    gather<Cd>(g, c, cls, gs, pg);
+    gather<Cd, HELD>(g, c, cls, gs, pg);
   using Sm = typename Cd::sum;
   Sm sE, sx, sy, sz;
   moment_sums(pg, sE, sx, sy, sz);
@@ -1071,14 +1098,19 @@ template <int FACES>
 __device__ __forceinline__ void lam_gather(const Geom &g, const Cell &c, const FaceCorr &fc,
                                            uint32_t cls, const LamT *__restrict__ R,
                                            double (&lam)[Q]) {
+  // x + e_p is the source of x's pull of opp(p) (src_fast applies its wrap
+  // corrections); bounce-back when that pull hits a solid (waves next to a
+  // solid gather again, as the forward pulls do)
 #pragma unroll
-  for (int p = 0; p < Q; ++p) {
-    // x + e_p is the source of x's pull of opp(p) (src_fast applies its wrap
-    // corrections); bounce-back when that pull hits a solid
-    const int q = OPP[p];
-    const bool bounce = (cls >> (CLS_BOUNCE + q)) & 1u;
-    const int src = bounce ? c.idx : src_fast(g, c, fc, q);
-    lam[p] = R[at(bounce ? q : p, src)];
+  for (int p = 0; p < Q; ++p) lam[p] = R[at(p, src_fast(g, c, fc, OPP[p]))];
+  if (wave_near_solid(cls)) {
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+      const int q = OPP[p];
+      const bool bounce = (cls >> (CLS_BOUNCE + q)) & 1u;
+      const int src = bounce ? c.idx : src_fast(g, c, fc, q);
+      lam[p] = R[at(bounce ? q : p, src)];
+    }
   }
   if (FACES == FACES_NONE) return;
   if (FACES != FACES_ANY) {
@@ -1164,7 +1196,11 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
     const FaceCorr fc = face_corr(g, c);
     double pre[Q], lam[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) pre[q] = (double)Cd::dec(S[pull_at(g, c, fc, cls, q)]);
+    for (int q = 0; q < Q; ++q) pre[q] = (double)Cd::dec(S[at(q, src_fast(g, c, fc, q))]);
+    if (wave_near_solid(cls)) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) pre[q] = (double)Cd::dec(S[pull_at(g, c, fc, cls, q)]);
+    }
     if (NAT_IN) {
 #pragma unroll
       for (int p = 0; p < Q; ++p) lam[p] = lam_in[at(p, c.idx)];

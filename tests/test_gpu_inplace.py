@@ -68,19 +68,35 @@ def test_inplace_small_sphere_matches_oracle():
 
 def test_inplace_sphere_block_against_two_buffer_run():
     """A 60 x 40 x 40 sphere over 40 steps (it goes unphysical on the way, as
-    the published scheme does at c_l = 1): the in-place and two-buffer GPU
-    runs have the same NaN cells and agree to rounding elsewhere."""
+    the published scheme does at c_l = 1).  Over the first 12 steps, while
+    the fields are still smooth, the in-place and two-buffer GPU runs agree
+    to 1e-12 at every other step.  Later the state is chaotic: a last-bit
+    difference between two differently compiled kernels grows by orders of
+    magnitude (measured between two builds of the two-buffer step kernel:
+    the first differing values, at step 16, differ by 2e-15; by step 40 by
+    up to 6e-9).  There the runs must have the same unphysical and
+    f-positivity counts after every pair of steps, the same NaN cells at the
+    end, and agree to 1e-6."""
     from paper_0912_2913_amd.solver import Solver
 
     mk = lambda: ri.sphere(nx=60, ny=40, nz=40, centre=(20, 20, 20), radius=6)
     a = Solver(mk())
-    a.step(40)
     b = Solver(inplace(mk()))
-    b.step(40)
+    ca, cb = np.zeros(2, np.int64), np.zeros(2, np.int64)
+    for step in range(2, 41, 2):  # the in-place state reads back after even step counts
+        a.step(2)
+        b.step(2)
+        ca += a.counters()
+        cb += b.counters()
+        assert tuple(ca) == tuple(cb), step
+        if step <= 12:
+            x, y = a.populations(), b.populations()
+            assert torch.allclose(x, y, rtol=1e-12, atol=1e-300), step
+    assert ca[0] > 0  # the run did go unphysical
     x, y = a.populations(), b.populations()
     assert torch.equal(torch.isnan(x), torch.isnan(y))
     f = ~torch.isnan(x)
-    assert torch.allclose(x[f], y[f], rtol=1e-12, atol=1e-300)
+    assert torch.allclose(x[f], y[f], rtol=1e-6, atol=1e-300)
     assert len(b.pop) == 1  # one state buffer
     a.close()
     b.close()
