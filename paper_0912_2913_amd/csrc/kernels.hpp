@@ -630,6 +630,127 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
 }
 
 // ---------------------------------------------------------------------------
+// Forward step with two cells per lane: cells 2t and 2t+1 of one x row, for
+// FP64 lattices with an even x extent and no held cells (no solid, no inflow
+// plane; constant or per-cell tau, not the eta/s rule).  The two cells'
+// sources of a pull with no x component are adjacent cells of one row with
+// the same wrap corrections, starting on an even cell: one aligned 16-byte
+// load reads both.  Pulls with an x component read the two sources apart.
+// Every store writes an aligned 16-byte pair.  g is pulled, relaxed and
+// stored before f is pulled, so that two cells' state of one population is
+// live at a time.  With held cells, or 4- and 2-byte storage, k_step is the
+// faster form and is kept.
+template <class El>
+struct Pair2 {
+  typedef El type __attribute__((ext_vector_type(2)));
+};
+
+template <class Cd>
+__device__ __forceinline__ void gather_pairs(const Geom &g, const Cell &c0, const Cell &c1,
+                                             const FaceCorr &f0, const FaceCorr &f1,
+                                             const typename Cd::elem *__restrict__ P,
+                                             typename Cd::calc (&v0)[Q],
+                                             typename Cd::calc (&v1)[Q]) {
+  using P2 = typename Pair2<typename Cd::elem>::type;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if (EX[q] == 0) {
+      const P2 pr = *reinterpret_cast<const P2 *>(&P[at(q, src_fast(g, c0, f0, q))]);
+      v0[q] = Cd::dec(pr.x);
+      v1[q] = Cd::dec(pr.y);
+    } else {
+      v0[q] = Cd::dec(P[at(q, src_fast(g, c0, f0, q))]);
+      v1[q] = Cd::dec(P[at(q, src_fast(g, c1, f1, q))]);
+    }
+  }
+}
+
+// Both cells' flags counted in one atomic per wave.
+__device__ __forceinline__ void count_pairs(bool f0, bool f1, unsigned long long *ctr, int k) {
+  const unsigned long long m0 = __ballot(f0), m1 = __ballot(f1);
+  if ((m0 | m1) != 0ull) {
+    const int lane = (int)(threadIdx.x & 63u);
+    if (lane == __ffsll((long long)(m0 | m1)) - 1)
+      atomicAdd(&ctr[(k * NSLOT + (int)(blockIdx.x & (NSLOT - 1))) * CSTRIDE],
+                (unsigned long long)(__popcll(m0) + __popcll(m1)));
+  }
+}
+
+// npb = workgroups per instance (each covers 2 * BLOCK cells).
+template <int ST, class TC>
+__global__ __launch_bounds__(BLOCK) void k_step_pairs(const Geom g, const Phys ph, int npb,
+                                                      const typename Codec<ST, TC>::elem *__restrict__ src,
+                                                      typename Codec<ST, TC>::elem *__restrict__ dst,
+                                                      unsigned long long *__restrict__ counters) {
+  using Cd = Codec<ST, TC>;
+  using T = typename Cd::calc;
+  using El = typename Cd::elem;
+  using Sm = typename Cd::sum;
+  using P2 = typename Pair2<El>::type;
+  Cell c0, c1;
+  c0.L = c1.L = xcd_remap((int)blockIdx.x, npb * g.batch);
+  c0.b = c1.b = c0.L / npb;
+  c0.local = 2 * ((c0.L - c0.b * npb) * BLOCK + (int)threadIdx.x);
+  if (c0.local >= g.per) return;  // the cell count per instance is even
+  c1.local = c0.local + 1;
+  const uint32_t t = fdiv(g.div_x, (uint32_t)c0.local);
+  c0.x = c0.local - (int)t * g.n[0];
+  c1.x = c0.x + 1;
+  const uint32_t z = fdiv(g.div_y, t);
+  c0.y = c1.y = (int)t - (int)z * g.n[1];
+  c0.z = c1.z = (int)z;
+  c0.idx = c0.b * g.per + c0.local;
+  c1.idx = c0.idx + 1;
+  c0.active = c1.active = true;
+  const FaceCorr f0 = face_corr(g, c0), f1 = face_corr(g, c1);
+  const El *__restrict__ gs = src + (size_t)Q * g.qs;
+  El *__restrict__ gd = dst + (size_t)Q * g.qs;
+  T p0[Q], p1[Q];
+  gather_pairs<Cd>(g, c0, c1, f0, f1, gs, p0, p1);
+  Sm e0, x0, y0, z0, e1, x1, y1, z1;
+  moment_sums(p0, e0, x0, y0, z0);
+  moment_sums(p1, e1, x1, y1, z1);
+  const Inv i0 = invert(ph, ph.e_ref + (double)e0, ph.c * (double)x0, ph.c * (double)y0,
+                        ph.c * (double)z0);
+  const Inv i1 = invert(ph, ph.e_ref + (double)e1, ph.c * (double)x1, ph.c * (double)y1,
+                        ph.c * (double)z1);
+  EqCoef<T> k0 = eq_coef<T>(ph, 0.0, i0.eps, i0.W, i0.bx, i0.by, i0.bz);
+  EqCoef<T> k1 = eq_coef<T>(ph, 0.0, i1.eps, i1.W, i1.bx, i1.by, i1.bz);
+  const T om0 = (T)omega_of(ph, c0.b, c0.idx), om1 = (T)omega_of(ph, c1.b, c1.idx);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    P2 o;
+    o.x = Cd::enc(p0[q] + om0 * (geq_dev(k0, q) - p0[q]));
+    o.y = Cd::enc(p1[q] + om1 * (geq_dev(k1, q) - p1[q]));
+    __builtin_nontemporal_store(o, reinterpret_cast<P2 *>(&gd[at(q, c0.idx)]));
+  }
+  count_pairs(i0.bad, i1.bad, counters, 0);
+  asm volatile("" ::: "memory");  // compiler barrier: f is pulled after g is stored
+  T q0[Q], q1[Q];
+  gather_pairs<Cd>(g, c0, c1, f0, f1, src, q0, q1);
+  Sm n0 = (Sm)0, n1 = (Sm)0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    n0 += (Sm)q0[q];
+    n1 += (Sm)q1[q];
+  }
+  const double N0 = ph.n_ref + (double)n0, N1 = ph.n_ref + (double)n1;
+  k0.N = (T)N0;
+  k0.Nd = (T)(N0 - ph.n_ref);
+  k1.N = (T)N1;
+  k1.Nd = (T)(N1 - ph.n_ref);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    P2 o;
+    o.x = Cd::enc(q0[q] + om0 * (feq_dev(k0, q) - q0[q]));
+    o.y = Cd::enc(q1[q] + om1 * (feq_dev(k1, q) - q1[q]));
+    __builtin_nontemporal_store(o, reinterpret_cast<P2 *>(&dst[at(q, c0.idx)]));
+  }
+  count_pairs(feq_nonpositive(i0.bx, i0.by, i0.bz, ph.inv_c),
+              feq_nonpositive(i1.bx, i1.by, i1.bz, ph.inv_c), counters, 1);
+}
+
+// ---------------------------------------------------------------------------
 // Initial state: equilibria of (n0, e0, beta0); inflow cells take the inflow
 // equilibrium; solid cells hold zeros in both buffers.
 template <int ST, class TC>

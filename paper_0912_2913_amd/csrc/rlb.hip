@@ -269,6 +269,22 @@ HeldEq<El> held_eq(const rlb_solver *h) {
   return v;
 }
 
+// Two cells per lane (16-byte accesses, k_step_pairs): FP64 storage, an even
+// x extent, no held cells, no eta/s rule.  Returns whether it launched.
+template <int ST, class TC>
+bool launch_step_pairs(rlb_solver *h, const typename Codec<ST, TC>::elem *src,
+                       typename Codec<ST, TC>::elem *dst) {
+  if constexpr (ST != ST_F64) {
+    return false;
+  } else {
+    if (h->held || h->ph.eta_s > 0.0 || h->g.n[0] % 2 != 0) return false;
+    const int npb = (h->g.per / 2 + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL((k_step_pairs<ST, TC>), dim3(npb * h->g.batch), dim3(BLOCK), 0, h->stream,
+                       h->g, h->ph, npb, src, dst, h->d_counters);
+    return true;
+  }
+}
+
 template <int ST, class TC>
 rlb_status launch_steps(rlb_solver *h, int nsteps) {
   using El = typename Codec<ST, TC>::elem;
@@ -303,7 +319,8 @@ rlb_status launch_steps(rlb_solver *h, int nsteps) {
     else if (etas)
       hipLaunchKernelGGL((k_step<ST, TC, true, false, true>), dim3(grid_blocks(h)), dim3(BLOCK),
                          0, h->stream, h->g, h->ph, src, dst, in_eq, h->d_counters);
-    else
+    else if (launch_step_pairs<ST, TC>(h, src, dst)) {
+    } else
       hipLaunchKernelGGL((k_step<ST, TC, true, false>), dim3(grid_blocks(h)), dim3(BLOCK), 0,
                          h->stream, h->g, h->ph, src, dst, in_eq, h->d_counters);
     h->cur = 1 - h->cur;

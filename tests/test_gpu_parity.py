@@ -136,6 +136,31 @@ def test_outflow_all_faces():
     compare(s, 30)
 
 
+def pair_cases():
+    """FP64 lattices without held cells and with an even x extent: the step
+    runs two cells per lane (16-byte pulls and stores)."""
+    tube = ri.random_state_setup(
+        2, 1, 5, seed=111, tau=[0.9], bc=((ri.OUTFLOW, ri.OUTFLOW), (ri.PERIODIC, ri.PERIODIC),
+                                          (ri.OUTFLOW, ri.OUTFLOW)))
+    eos = ri.random_state_setup(12, 9, 10, batch=2, seed=112, tau=[0.7, 1.1], c_l=2.0,
+                                bc=((ri.OUTFLOW, ri.OUTFLOW),) * 3)
+    eos.kappa = 0.25
+    field = ri.random_state_setup(14, 11, 9, batch=3, seed=113, tau=[0.6, 0.8, 1.0])
+    field.tau_cell = np.random.default_rng(8).uniform(0.55, 1.3, field.cells)
+    return {
+        # 1386 cells per instance: 3 workgroups of 512 cells, the last ragged
+        "batch_ragged": ri.random_state_setup(14, 11, 9, batch=3, seed=110, tau=[0.55, 0.9, 1.4]),
+        "two_cell_rows_outflow": tube,
+        "outflow_kappa_tachyon_batch": eos,
+        "tau_field_batch": field,
+    }
+
+
+@pytest.mark.parametrize("name", list(pair_cases()))
+def test_two_cells_per_lane_step(name):
+    compare(pair_cases()[name], 30)
+
+
 def test_inflow_outflow_obstacle():
     """x: inflow / outflow, y periodic, z outflow, solid ball, 2 instances."""
     s = ri.random_state_setup(
