@@ -238,6 +238,7 @@ def bench_adjoint(s, T, warmup, reps=4, mode="sqrt"):
     alone (one sweep over an innermost segment's states)."""
     import torch
 
+    import rlb_inputs as ri
     from paper_0912_2913_amd.autograd import GRun, peak_states, schedule
     from paper_0912_2913_amd.solver import Solver
 
@@ -274,7 +275,22 @@ def bench_adjoint(s, T, warmup, reps=4, mode="sqrt"):
 
     sweep(0)
     t_sw = time_steps(sweep, 0, sv.stream) / (reps * S)
+
+    # the reverse kernel alone, as the schedule's segments run it: lambda read
+    # and written in reader form, one launch per step
+    def segments(_):
+        for _r in range(reps):
+            sv.adjoint_segment(seq[0], seq[1:], S, la, lb, in_reader=True, out_reader=True)
+
+    segments(0)
+    t_k = time_steps(segments, 0, sv.stream) / (reps * S)
     sv.adjoint_flush()
+    # algorithmic bytes per launch: per updated cell the pulled g state (19
+    # values of the storage) and lambda in and out (19 FP64 values each)
+    ab = algorithmic_bytes(s, 8)
+    elem = {ri.F64: 8, ri.F32: 4, ri.F32DEV: 4, ri.F16DEV: 2, ri.BF16DEV: 2}[s.storage]
+    k_bytes = ab["updated_cells"] * Q * (elem + 8 + 8)
+    k_gbs = k_bytes / t_k / 1e9
     run.close()
     sv.close()
     del sv, run, seq, la, lb
@@ -283,7 +299,11 @@ def bench_adjoint(s, T, warmup, reps=4, mode="sqrt"):
             "forward_ms": 1e3 * fwd,
             "checkpointed_g_forward_ms": 1e3 * t_gf, "reverse_sweep_ms": 1e3 * t_bw,
             "adjoint_ms": 1e3 * t_sw, "ratio": t_bw / fwd, "gradient_ratio": (t_gf + t_bw) / fwd,
-            "adjoint_kernel_ratio": t_sw / fwd}
+            "adjoint_kernel_ratio": t_sw / fwd,
+            "adjoint_kernel_alone_ms": 1e3 * t_k, "adjoint_kernel_alone_ratio": t_k / fwd,
+            "adjoint_kernel_roofline": {"achieved": round(k_gbs, 1), "unit": "GB/s",
+                                        "frac": round(k_gbs / HBM_PEAK_GBS, 4),
+                                        "bytes_per_launch": int(k_bytes)}}
 
 
 def bench_large_gradient(T=4000, modes=("sqrt", "3level")):
