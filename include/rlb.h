@@ -354,6 +354,18 @@ rlb_status rlb_transport(rlb_solver *h, double d_G, double *T, double *s, double
  * sum of dL/dtau(x) over its cells.) */
 rlb_status rlb_adjoint_flush_tau_field(rlb_solver *h, double *dL_dtau_cell);
 
+/* The 16-bit storages' encoder (rlb_storage RLB_F16DEV / RLB_BF16DEV: the
+ * deviations from the rest equilibrium stored as binary16 or bfloat16), on n
+ * FP32 values: dst[i] is the element the step kernels store for the value
+ * src[i], rounded to nearest, ties to even (bfloat16: the upper 16 bits of
+ * the binary32 pattern after rounding on the discarded 16 bits; NaN stays
+ * NaN; overflow gives infinity).  For callers that encode deviations
+ * themselves.  storage: RLB_F16DEV or RLB_BF16DEV; src: device float [n];
+ * dst: device 2-byte elements [n]; stream: a hipStream_t, NULL for the null
+ * stream.  Enqueued, not synchronised; needs no solver.  RLB_EINVAL for
+ * another storage, n < 0, or a NULL pointer with n > 0. */
+rlb_status rlb_encode16(int32_t storage, const float *src, void *dst, int64_t n, void *stream);
+
 /* Release the solver's own memory (not pop_a / pop_b).  Synchronises. */
 rlb_status rlb_destroy(rlb_solver *h);
 

@@ -24,7 +24,7 @@ EXPORTS = (
     "rlb_destroy", "rlb_status_string", "rlb_last_error", "rlb_advance_g", "rlb_trajectory_g",
     "rlb_adjoint_sweep", "rlb_adjoint_flush", "rlb_set_tau_field", "rlb_hold_eta_over_s",
     "rlb_transport", "rlb_adjoint_flush_tau_field", "rlb_moments_noalloc", "rlb_adjoint_segment",
-    "rlb_lam_gather",
+    "rlb_lam_gather", "rlb_encode16",
 )
 LAM_IN_READER, LAM_OUT_READER = 1, 2
 
@@ -88,6 +88,7 @@ def lib():
     L.rlb_adjoint_segment.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp,
                                       ctypes.c_int32, ctypes.POINTER(vp)]
     L.rlb_lam_gather.argtypes = [vp, vp, vp]
+    L.rlb_encode16.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int64, vp]
     L.rlb_set_tau_field.argtypes = [vp, vp]
     L.rlb_hold_eta_over_s.argtypes = [vp, ctypes.c_double, ctypes.c_double]
     L.rlb_transport.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
@@ -104,7 +105,7 @@ def lib():
                  "rlb_init_adjoint", "rlb_destroy", "rlb_advance_g", "rlb_trajectory_g",
                  "rlb_adjoint_sweep", "rlb_adjoint_flush", "rlb_set_tau_field",
                  "rlb_hold_eta_over_s", "rlb_transport", "rlb_adjoint_flush_tau_field",
-                 "rlb_moments_noalloc", "rlb_adjoint_segment", "rlb_lam_gather"):
+                 "rlb_moments_noalloc", "rlb_adjoint_segment", "rlb_lam_gather", "rlb_encode16"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

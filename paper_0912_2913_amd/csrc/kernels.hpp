@@ -750,6 +750,17 @@ __global__ __launch_bounds__(BLOCK) void k_step_pairs(const Geom g, const Phys p
               feq_nonpositive(i1.bx, i1.by, i1.bz, ph.inv_c), counters, 1);
 }
 
+// The 16-bit storages' encoder on n FP32 values (the conversion the step's
+// stores apply); grid-stride.
+template <int ST>
+__global__ __launch_bounds__(BLOCK) void k_encode16(const float *__restrict__ src,
+                                                    typename Format<ST>::elem *__restrict__ dst,
+                                                    long long n) {
+  const long long stride = (long long)gridDim.x * BLOCK;
+  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride)
+    dst[i] = Format<ST>::enc(src[i]);
+}
+
 // ---------------------------------------------------------------------------
 // Initial state: equilibria of (n0, e0, beta0); inflow cells take the inflow
 // equilibrium; solid cells hold zeros in both buffers.

@@ -2,6 +2,7 @@
 // dispatch and the C entry points declared in include/rlb.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1155,6 +1156,24 @@ rlb_status rlb_destroy(rlb_solver *h) {
   hipError_t e = hipStreamSynchronize(h->stream);
   free_solver(h);
   if (e != hipSuccess) return fail(RLB_EDEVICE, hipGetErrorString(e));
+  return RLB_OK;
+}
+
+rlb_status rlb_encode16(int32_t storage, const float *src, void *dst, int64_t n, void *stream) {
+  if ((storage != RLB_F16DEV && storage != RLB_BF16DEV) || n < 0 || (n > 0 && (!src || !dst)))
+    return fail(RLB_EINVAL, "rlb_encode16: storage must be RLB_F16DEV or RLB_BF16DEV, n >= 0, "
+                            "non-NULL buffers");
+  if (n == 0) return RLB_OK;
+  const long long want = (n + BLOCK - 1) / BLOCK;
+  const unsigned blocks = (unsigned)std::min<long long>(want, 1 << 20);
+  const hipStream_t st = (hipStream_t)stream;
+  if (storage == RLB_F16DEV)
+    hipLaunchKernelGGL(k_encode16<ST_F16DEV>, dim3(blocks), dim3(BLOCK), 0, st, src,
+                       (_Float16 *)dst, (long long)n);
+  else
+    hipLaunchKernelGGL(k_encode16<ST_BF16DEV>, dim3(blocks), dim3(BLOCK), 0, st, src,
+                       (uint16_t *)dst, (long long)n);
+  RLB_HIP(hipGetLastError());
   return RLB_OK;
 }
 
