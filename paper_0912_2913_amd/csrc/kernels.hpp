@@ -493,11 +493,13 @@ __device__ __forceinline__ size_t pull_at(const Geom &g, const Cell &c, const Fa
 
 // A wave holds a cell with a solid pull source (the cell word's near bit).
 // Such waves are few (the cells next to an obstacle).  For 4- and 8-byte
-// populations the pulls below are issued with the plain offsets before the
-// cell word has arrived, and only these waves pull again with the bounce-back
-// offsets, so that no wave waits for its cell words before its population
-// loads.  The 16-bit forms are issue-bound: there the second pull's code costs
-// more than the wait, and the offsets are selected from the cell word.
+// populations the gathers below are written as plain pulls followed, in those
+// waves only, by pulls with the bounce-back offsets: this compiles to one
+// branch per wave on the near bit, and the other waves pull without the
+// per-direction offset selects.  (Issuing the plain pulls before the cell
+// word arrives, with per-lane bounce-back loads after it, measured slower:
+// those loads wait inside their branches.)  The 16-bit forms are issue-bound
+// and keep the offsets selected from the cell word in every wave.
 __device__ __forceinline__ bool wave_near_solid(uint32_t cls) {
   return __builtin_amdgcn_ballot_w64((cls & CLS_NEAR) != 0u) != 0u;
 }
