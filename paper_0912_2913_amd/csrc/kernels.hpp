@@ -1433,7 +1433,6 @@ __global__ __launch_bounds__(BLOCK) void k_init_adjoint(
     const Geom g, const Phys ph, const double *__restrict__ e0, const double *__restrict__ beta0,
     const typename Codec<ST, TC>::lam *__restrict__ lam0, double *__restrict__ de0,
     double *__restrict__ db0, double *__restrict__ part, const InflowState in) {
-  using Cd = Codec<ST, TC>;
   using T = double;  // reverse-mode arithmetic is FP64 for every storage
   const Cell c = decode_cell(g);
   const size_t cells = (size_t)g.batch * g.per;
@@ -1572,9 +1571,9 @@ __device__ __forceinline__ uint32_t collide_emit(const Phys &ph, const Cell &c,
 // Relax both populations of one update in place (pre -> post) with the same
 // arithmetic as k_step; returns the update's event flags.
 template <class Cd>
-__device__ __forceinline__ uint32_t collide_inplace(const Geom &g, const Phys &ph, const Cell &c,
-                                                typename Cd::calc (&pg)[Q],
-                                                typename Cd::calc (&pf)[Q]) {
+__device__ __forceinline__ uint32_t collide_inplace(const Phys &ph, const Cell &c,
+                                                    typename Cd::calc (&pg)[Q],
+                                                    typename Cd::calc (&pf)[Q]) {
   using T = typename Cd::calc;
   using Sm = typename Cd::sum;
   Sm sE, sx, sy, sz;
@@ -1804,7 +1803,7 @@ __device__ __forceinline__ uint32_t aa_pull_general(const Geom &g, const Phys &p
         pg[q] = Cd::dec(Ag[o]);
       }
     }
-    ev = collide_inplace<Cd>(g, ph, c, pg, pf);
+    ev = collide_inplace<Cd>(ph, c, pg, pf);
   }
   // one instance of the body per direction (q a constant, so that pf[q] and
   // pg[q] stay in registers and impossible clamp patterns fold away)
