@@ -34,6 +34,10 @@ def setups():
             11, 6, 7, batch=2, seed=206, tau=[0.7, 0.95],
             bc=((ri.INFLOW, ri.OUTFLOW), (ri.PERIODIC, ri.PERIODIC), (ri.PERIODIC, ri.PERIODIC)),
             inflow=(1.0, 1.02, 0.12, 0.02, -0.03), solid_centre=(10, 3, 3), solid_radius=1.8),
+        "thin_outflow_axis_and_inflow": ri.random_state_setup(
+            5, 2, 4, seed=207, tau=[0.85],
+            bc=((ri.INFLOW, ri.OUTFLOW), (ri.OUTFLOW, ri.OUTFLOW), (ri.PERIODIC, ri.PERIODIC)),
+            inflow=(1.0, 1.0, 0.1, 0.0, 0.02), solid_centre=(3, 1, 2), solid_radius=0.9),
         "tube_batch": ri.shock_tube(nz=67, e_L=1.0, e_R=0.3, tau=0.7, batch=3),
         "tachyon": ri.random_state_setup(6, 7, 5, seed=205, tau=[0.9], c_l=2.0,
                                          bc=((ri.PERIODIC, ri.PERIODIC), (ri.OUTFLOW, ri.OUTFLOW),
@@ -313,7 +317,8 @@ def test_adjoint_sweep_equals_pending_adjoint_steps(name):
 
 
 @pytest.mark.parametrize("name", ["inflow_outflow_obstacle", "outflow_corners",
-                                  "inflow_x_solid_on_outflow_face", "tube_batch"])
+                                  "inflow_x_solid_on_outflow_face", "thin_outflow_axis_and_inflow",
+                                  "tube_batch"])
 def test_reader_form_segments_equal_step_by_step(name):
     """Segments chained in reader form (a checkpoint read in place plus its
     successors per call, one gather at the end) give the lambda and the
