@@ -1656,11 +1656,14 @@ __global__ __launch_bounds__(BLOCK) void k_mark_aa(const Geom g, const Phys ph,
 }
 
 // Face copies of one cell's post-collision values (one per non-periodic face
-// the cell lies on).
+// the cell lies on).  Only the directions that a clamped pull reads are
+// copied: a pull of q clamped onto the low face of axis a has e_qa = +1, onto
+// the high face e_qa = -1 (five directions per face).
 template <class El, class VF, class VG>
 __device__ __forceinline__ void aa_face_copies(const Geom &g, const FaceMap &fm, const Cell &c,
                                                El *__restrict__ Fb, const VF &of, const VG &og) {
   const int co[3] = {c.x, c.y, c.z};
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (g.periodic[a]) continue;
     const int sd = co[a] == 0 ? 0 : (co[a] == g.n[a] - 1 ? 1 : -1);
@@ -1668,6 +1671,8 @@ __device__ __forceinline__ void aa_face_copies(const Geom &g, const FaceMap &fm,
     const long long t = face_pos(g, fm, fm.id[a][sd], a, c.b, c.x, c.y, c.z);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
+      const int e = a == 0 ? EX[q] : (a == 1 ? EY[q] : EZ[q]);  // compile-time
+      if (e == 0 || (e == 1) != (sd == 0)) continue;
       Fb[(size_t)q * fm.nf + t] = of(q);
       Fb[(size_t)(Q + q) * fm.nf + t] = og(q);
     }

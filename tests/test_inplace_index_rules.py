@@ -3,7 +3,8 @@
 A model of the two in-place kernels' reads and writes (the pull kernel: pull
 from the swapped layout, push each post-collision value to every cell that
 will pull it, clamped pulls through per-face copies; the local kernel: collide
-in place, store into the opposite slot, refresh the face copies) is run on
+in place, store into the opposite slot, refresh the face copies of the
+directions a clamped pull reads) is run on
 unique labels with the collision replaced by the identity, so that only data
 movement remains.  Checked:
 
@@ -163,6 +164,9 @@ def local_kernel(L: Lat, A, Fb, held, acc: Access):
             for a, side in L.faces_of(c):
                 t = L.face_pos(L.face_id[(a, side)], a, c)
                 for q in range(Q):
+                    # only the directions a clamped pull onto this face reads
+                    if E[q][a] != (1 if side == 0 else -1):
+                        continue
                     acc.write("F", (q, t), i)
                     newF[q, t] = post[q]
     return newA, newF
