@@ -1355,7 +1355,8 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
     const bool held = solid || inflow;
     const LocalAdjoint a = adjoint_local(ph, omega_of(ph, c.b, c.idx), pre, lam);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) R_out[at(q, c.idx)] = held ? 0.0 : adjoint_mu(a, lam[q], q);
+    for (int q = 0; q < Q; ++q)
+      stream_store(&R_out[at(q, c.idx)], held ? 0.0 : adjoint_mu(a, lam[q], q));
     if (!held) {
       acc[0] = a.dtau;
       if (ph.dtau_cell) ph.dtau_cell[c.idx] += a.dtau;
@@ -1384,7 +1385,7 @@ __global__ __launch_bounds__(BLOCK) void k_lam_gather(const Geom g, const Phys p
   double v[Q];
   lam_gather<FACES>(g, c, fc, cls, R, v);
 #pragma unroll
-  for (int p = 0; p < Q; ++p) lam[at(p, c.idx)] = solid ? 0.0 : v[p];
+  for (int p = 0; p < Q; ++p) stream_store(&lam[at(p, c.idx)], solid ? 0.0 : v[p]);
 }
 
 // Faces of non-periodic axes, flattened: face f = (axis, side) holds
