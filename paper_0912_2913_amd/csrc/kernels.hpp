@@ -633,15 +633,16 @@ __global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Phys ph,
 
 // ---------------------------------------------------------------------------
 // Forward step with two cells per lane: cells 2t and 2t+1 of one x row, for
-// FP64 lattices with an even x extent and no held cells (no solid, no inflow
-// plane; constant or per-cell tau, not the eta/s rule).  The two cells'
-// sources of a pull with no x component are adjacent cells of one row with
-// the same wrap corrections, starting on an even cell: one aligned 16-byte
-// load reads both.  Pulls with an x component read the two sources apart.
-// Every store writes an aligned 16-byte pair.  g is pulled, relaxed and
-// stored before f is pulled, so that two cells' state of one population is
-// live at a time.  With held cells, or 4- and 2-byte storage, k_step is the
-// faster form and is kept.
+// lattices with an even x extent and no held cells (no solid, no inflow
+// plane; constant or per-cell tau, not the eta/s rule), in FP64 storage or
+// FP32 storage with FP64 collision.  The two cells' sources of a pull with no
+// x component are adjacent cells of one row with the same wrap corrections,
+// starting on an even cell: one aligned load of two elements reads both.
+// Pulls with an x component read the two sources apart.  Every store writes
+// an aligned pair.  g is pulled, relaxed and stored before f is pulled, so
+// that two cells' state of one population is live at a time.  With held
+// cells, 2-byte storage or FP32 collision k_step is kept (measured faster, or
+// the moment correction of the FP32 collision is not part of this kernel).
 template <class El>
 struct Pair2 {
   typedef El type __attribute__((ext_vector_type(2)));

@@ -270,12 +270,15 @@ HeldEq<El> held_eq(const rlb_solver *h) {
   return v;
 }
 
-// Two cells per lane (16-byte accesses, k_step_pairs): FP64 storage, an even
-// x extent, no held cells, no eta/s rule.  Returns whether it launched.
+// Two cells per lane (k_step_pairs): FP64 storage, or FP32 / FP32-deviation
+// storage with FP64 collision; an even x extent, no held cells, no eta/s
+// rule.  Returns whether it launched.
 template <int ST, class TC>
 bool launch_step_pairs(rlb_solver *h, const typename Codec<ST, TC>::elem *src,
                        typename Codec<ST, TC>::elem *dst) {
-  if constexpr (ST != ST_F64) {
+  constexpr bool pairs = ST == ST_F64 ||
+                         ((ST == ST_F32 || ST == ST_F32DEV) && std::is_same<TC, double>::value);
+  if constexpr (!pairs) {
     return false;
   } else {
     if (h->held || h->ph.eta_s > 0.0 || h->g.n[0] % 2 != 0) return false;
